@@ -1,0 +1,169 @@
+/*
+ * blip.h -- C ABI of libblip: periodic cubic B-spline ("blip") orbital
+ * evaluation on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Sec. II.B "Orbital evaluation", Eqs. (11.12.24.1),
+ * (11.12.24.2) and (7)): every orbital psi_l is a sum over a periodic grid
+ * of coefficients a_{l,s} times a tensor product of 1-D cubic B-splines;
+ * at a position only the 4x4x4 sites around it contribute.  libblip keeps
+ * the coefficient table resident on the GPU (loaded once, as the paper's
+ * precomputed input file is) and evaluates psi_l, grad psi_l and
+ * lap psi_l for all L orbitals at a block of positions -- the block of
+ * trial moves that quasi-simultaneous updating (Sec. III.A, Eqs.
+ * (11.12.23.1)-(11.12.23.2)) produces once per Monte Carlo step.
+ *
+ * Conventions shared by every call:
+ *  - Device pointers are HIP device memory of the current device; host
+ *    pointers are ordinary host memory.  Sizes are in elements.
+ *  - Positions are Cartesian bohr, float64, [npos][3], unwrapped: the
+ *    library wraps them into the cell in FP64.
+ *  - Outputs are orbital-contiguous rows: val [npos][L], grad [npos][3][L],
+ *    lap [npos][L]; float for real tables, float2 (re, im) for complex ones.
+ *    Accumulation is FP32 (FP64 in the debug kernel of blip_eval_ex).
+ *  - Gradients are in bohr^-1, Laplacians in bohr^-2.
+ *  - Every call returns BLIP_OK (0) or a negative status; the message for
+ *    the last non-zero status on the calling thread is blip_last_error().
+ *    Argument errors are reported before anything is enqueued.
+ *  - Evaluation calls are asynchronous and stream-ordered on the caller's
+ *    stream (a hipStream_t passed as void*, NULL = the null stream); they
+ *    never synchronise.  Faults on the device surface at the caller's next
+ *    synchronisation as HIP errors.
+ *  - A table is immutable after blip_load; evaluation calls on one table may
+ *    run concurrently on different streams.
+ *  - Non-finite positions never cause out-of-bounds reads: their output
+ *    rows are NaN.
+ */
+#ifndef BLIP_H
+#define BLIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLIP_API __attribute__((visibility("default")))
+
+typedef struct blip_table_s* blip_table;   /* opaque; owned by the library */
+
+/* Storage dtype of the resident table.  The caller always hands over an
+ * FP32 master (float, or float2 for complex); reduced-precision storage is
+ * produced on the device by round-to-nearest-even. */
+typedef enum {
+    BLIP_F32 = 0,     /* real, float                                      */
+    BLIP_BF16 = 1,    /* real, bfloat16                                   */
+    BLIP_F16 = 2,     /* real, IEEE half with a power-of-two table scale  */
+    BLIP_C64 = 3,     /* complex, float2                                  */
+    BLIP_CBF16 = 4,   /* complex, bfloat16 (re, im) pairs                 */
+    BLIP_CF16 = 5     /* complex, half (re, im) pairs with a 2^e scale    */
+} blip_dtype;
+
+enum {
+    BLIP_OK = 0,
+    BLIP_E_ARG = -1,     /* bad argument (sizes, NULL, singular lattice)   */
+    BLIP_E_OOM = -2,     /* device allocation failed                       */
+    BLIP_E_HIP = -3,     /* a HIP runtime call failed                      */
+    BLIP_E_DTYPE = -4,   /* dtype not valid for this table / request       */
+    BLIP_E_ALIGN = -5,   /* pointer not 16-byte aligned                    */
+    BLIP_E_STATE = -6,   /* invalid handle or object state                 */
+    BLIP_E_NODEV = -7    /* no usable gfx950 device                        */
+};
+
+/* Evaluation kernels selectable through blip_eval_ex. */
+typedef enum {
+    BLIP_KERNEL_AUTO = 0,   /* tuned tiled kernel (what blip_eval runs)        */
+    BLIP_KERNEL_PLAIN = 1,  /* one workgroup per position, one lane per orbital,
+                               64 x 5 weights in LDS: the paper's coalesced
+                               mapping (Sec. III.B) written for wave64         */
+    BLIP_KERNEL_TILED = 2,  /* P positions per workgroup, separable 1-D weights,
+                               o orbitals per lane with wide loads             */
+    BLIP_KERNEL_F64ACC = 3  /* tiled kernel with FP64 accumulation (debug;
+                               real FP32 tables only)                          */
+} blip_kernel;
+
+typedef struct {
+    int kernel;          /* blip_kernel                                       */
+    int tile_pos;        /* P: positions per workgroup (1..64), 0 = tuned     */
+    int vec;             /* o: table elements per lane per load (1, 2, 4, 8),
+                            0 = tuned                                          */
+} blip_eval_opts;
+
+/*
+ * blip_load -- copy a coefficient table to the device and keep it resident.
+ * (The precomputed coefficients a~_{l,s~} of Eq. (7), loaded once at start.)
+ *
+ *  lattice     host double[9]: rows a_1, a_2, a_3 of the periodic cell, bohr.
+ *              Must be finite and non-singular.
+ *  n1, n2, n3  grid points along a_1, a_2, a_3; each >= 4.  Site (i1,i2,i3)
+ *              sits at sum_d (i_d / n_d) a_d.
+ *  norb        number of orbitals L >= 1.
+ *  coeffs_host host array [n1][n2][n3][norb] in C order (orbital fastest):
+ *              float for real storage dtypes, float2 (re, im) for complex.
+ *              Read during the call only; the library keeps its own copy.
+ *  storage     blip_dtype of the resident copy.
+ *  kvec        host double[3] k-point (bohr^-1) for complex tables, giving
+ *              psi = exp(i k.r) u with u the spline sum; NULL = Gamma.
+ *              A kvec with a real storage dtype is BLIP_E_DTYPE.
+ *  out         receives the handle (NULL on failure).
+ * Device memory: n1*n2*n3 rows of roundup(L * element bytes, 128) bytes.
+ * Synchronous: returns after the table is resident.  Errors: BLIP_E_ARG,
+ * BLIP_E_DTYPE, BLIP_E_OOM, BLIP_E_HIP, BLIP_E_NODEV.
+ */
+BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3,
+                       int norb, const void* coeffs_host, blip_dtype storage,
+                       const double kvec[3], blip_table* out);
+
+/*
+ * blip_eval -- evaluate all orbitals at a block of positions (Eq.
+ * (11.12.24.1) for every j of the block; the N x L independent evaluations
+ * of quasi-simultaneous updating, Sec. III.A).
+ *
+ *  t     handle from blip_load.
+ *  pos   device double[npos][3], Cartesian bohr, any values (wrapped in FP64).
+ *  npos  >= 0; 0 returns BLIP_OK and enqueues nothing.
+ *  val   device [npos][L] float (real) or float2 (complex); required.
+ *  grad  device [npos][3][L]; lap device [npos][L].  Pass both or neither:
+ *        grad == lap == NULL runs the values-only kernel.
+ *  stream hipStream_t (as void*), NULL = null stream.
+ * pos, val, grad and lap must be 16-byte aligned (BLIP_E_ALIGN); the caller
+ * owns them and keeps them alive until the stream has run the work.
+ * Runs the tuned tiled kernel.  No allocation, no synchronisation.
+ */
+BLIP_API int blip_eval(blip_table t, const double* pos, int64_t npos,
+                       void* val, void* grad, void* lap, void* stream);
+
+/*
+ * blip_eval_ex -- blip_eval with an explicit kernel choice (opts may be NULL
+ * for the defaults).  Same arguments, layouts and errors as blip_eval;
+ * BLIP_E_ARG for P outside 1..64 or an unsupported o for the storage dtype,
+ * BLIP_E_DTYPE for BLIP_KERNEL_F64ACC on anything but BLIP_F32.
+ * Every kernel and every (P, o) computes each output with the same sequence
+ * of operations, so results agree bit for bit across tilings
+ * (BLIP_KERNEL_PLAIN and BLIP_KERNEL_F64ACC round differently).
+ */
+BLIP_API int blip_eval_ex(blip_table t, const double* pos, int64_t npos,
+                          void* val, void* grad, void* lap,
+                          const blip_eval_opts* opts, void* stream);
+
+/* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
+ * total device bytes.  Any output pointer may be NULL. */
+BLIP_API int blip_table_info(blip_table t, int* norb, int* storage,
+                             int64_t* row_bytes, int64_t* device_bytes);
+
+/* blip_free -- release the table's device memory (synchronises the device
+ * first so in-flight work finishes).  NULL is accepted and ignored. */
+BLIP_API int blip_free(blip_table t);
+
+/* blip_last_error -- thread-local message for the last non-zero status
+ * returned on the calling thread ("" if none).  Owned by the library. */
+BLIP_API const char* blip_last_error(void);
+
+/* blip_version -- library version string (static storage). */
+BLIP_API const char* blip_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLIP_H */

@@ -1,0 +1,152 @@
+"""FP64 CPU oracle for blip orbital evaluation -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it; the two meet only at the seeded input generators.
+
+Two independent formulations live here:
+
+* :func:`evaluate` -- the plain definition of Eq. (11.12.24.1)/(11.12.24.2)
+  in C (``blip_oracle.c``): wrap, select the 4x4x4 site subset of Eq. (7),
+  sum a_{l,s} Theta_s with Theta_s and its derivatives from the cubic
+  B-spline written by cases of |x|.
+* :mod:`oracle.brute` -- a NumPy brute force over *every* coefficient of a
+  tiny grid and its periodic images, with the spline written in
+  truncated-power form.  It pins the C oracle.
+
+Inputs are NumPy arrays; outputs are float64 (complex128 for complex tables).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "blip_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_KIND = {np.dtype(np.float64): 0, np.dtype(np.float32): 1,
+         np.dtype(np.complex128): 2, np.dtype(np.complex64): 3}
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    for name in ("oracle_phi", "oracle_dphi", "oracle_d2phi"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_double
+        fn.argtypes = [ctypes.c_double]
+    lib.oracle_inverse3.restype = ctypes.c_int
+    lib.oracle_inverse3.argtypes = [dp, dp]
+    lib.oracle_wrap.restype = ctypes.c_int
+    lib.oracle_wrap.argtypes = [dp, ip, dp, ip, dp]
+    lib.oracle_eval.restype = ctypes.c_int
+    lib.oracle_eval.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                dp, dp, ctypes.c_int64, dp, dp, dp,
+                                ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def phi(x, deriv: int = 0) -> np.ndarray:
+    """The 1-D cubic B-spline phi (deriv 0), phi' (1) or phi'' (2)."""
+    lib = _load()
+    fn = (lib.oracle_phi, lib.oracle_dphi, lib.oracle_d2phi)[deriv]
+    xs = np.asarray(x, dtype=np.float64)
+    return np.vectorize(lambda v: fn(float(v)), otypes=[np.float64])(xs)
+
+
+def inverse3(lattice) -> np.ndarray:
+    """A^{-1} by cofactors, as the oracle forms it (raises if singular)."""
+    lib = _load()
+    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    G = np.zeros(9)
+    if lib.oracle_inverse3(_dptr(A), _dptr(G)) != 0:
+        raise ValueError("singular lattice")
+    return G.reshape(3, 3)
+
+
+def wrap(lattice, n, r):
+    """Cell index i0 and offset f of position r (the subset selection, Eq. (7))."""
+    lib = _load()
+    G = np.ascontiguousarray(inverse3(lattice).reshape(9))
+    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+    rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
+    i0 = (ctypes.c_int * 3)()
+    f = np.zeros(3)
+    rc = lib.oracle_wrap(_dptr(G), nn, _dptr(rr), i0, _dptr(f))
+    return np.array(list(i0), dtype=np.int64), f, rc == 0
+
+
+def evaluate(lattice, n, coef, pos, kvec=None, want=("val", "grad", "lap"),
+             nthreads: int = 1):
+    """Orbitals (and gradients, Laplacians) at every position, in FP64.
+
+    lattice: 3x3 rows a_1..a_3 (bohr); n: (n1, n2, n3);
+    coef: array [n1, n2, n3, L] of float64/float32/complex128/complex64;
+    pos: [npos, 3] Cartesian bohr; kvec: k-point (complex tables only).
+    Returns a dict with ``val`` [npos, L], ``grad`` [npos, 3, L] and
+    ``lap`` [npos, L] for the requested keys.
+    """
+    lib = _load()
+    coef = np.ascontiguousarray(coef)
+    if coef.dtype not in _KIND:
+        raise TypeError(f"unsupported coefficient dtype {coef.dtype}")
+    n1, n2, n3 = (int(v) for v in n)
+    if coef.ndim != 4 or coef.shape[:3] != (n1, n2, n3):
+        raise ValueError("coef must be [n1, n2, n3, L]")
+    L = int(coef.shape[3])
+    cplx = np.iscomplexobj(coef)
+    pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+    npos = pos.shape[0]
+    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    odt = np.complex128 if cplx else np.float64
+    out = {}
+    if "val" in want:
+        out["val"] = np.zeros((npos, L), dtype=odt)
+    if "grad" in want:
+        out["grad"] = np.zeros((npos, 3, L), dtype=odt)
+    if "lap" in want:
+        out["lap"] = np.zeros((npos, L), dtype=odt)
+    k = None
+    if kvec is not None:
+        k = np.ascontiguousarray(np.asarray(kvec, dtype=np.float64).reshape(3))
+    null = ctypes.POINTER(ctypes.c_double)()
+    rc = lib.oracle_eval(
+        _dptr(A), n1, n2, n3, L, coef.ctypes.data_as(ctypes.c_void_p),
+        _KIND[coef.dtype], _dptr(k) if k is not None else null,
+        _dptr(pos), npos,
+        _dptr(out["val"]) if "val" in out else null,
+        _dptr(out["grad"]) if "grad" in out else null,
+        _dptr(out["lap"]) if "lap" in out else null,
+        int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_eval rejected its arguments")
+    return out
