@@ -37,7 +37,10 @@ def bspline3(x, deriv=0):
             acc = acc + _BINOM4[k] * 3.0 * _tp(y, 2) / 6.0
         else:
             acc = acc + _BINOM4[k] * 6.0 * _tp(y, 1) / 6.0
-    return acc
+    # Outside (-2, 2) the truncated powers cancel exactly in real arithmetic;
+    # in floating point they leave a residue of order (x+2)^3 eps, so the
+    # identically-zero region is set to zero explicitly.
+    return np.where(np.abs(x) < 2.0, acc, 0.0)
 
 
 def evaluate(lattice, n, coef, pos, kvec=None):
