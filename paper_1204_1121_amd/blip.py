@@ -1,0 +1,173 @@
+"""Python binding of libblip (ctypes): argument marshalling only.
+
+Every step of the evaluation runs in the HIP kernels of ``libblip.so``;
+this module hands torch device pointers and the current torch stream to
+the C ABI (include/blip.h) and raises on a non-zero status.  There is no
+CPU fallback: if the library is missing, importing the binding raises.
+
+PyTorch is used for device memory and streams only.  It must be imported
+before the library is loaded so that both share one HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libblip.so")
+
+BLIP_OK = 0
+STATUS = {0: "BLIP_OK", -1: "BLIP_E_ARG", -2: "BLIP_E_OOM", -3: "BLIP_E_HIP",
+          -4: "BLIP_E_DTYPE", -5: "BLIP_E_ALIGN", -6: "BLIP_E_STATE",
+          -7: "BLIP_E_NODEV"}
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2, "c64": 3, "cbf16": 4, "cf16": 5}
+KERNEL = {"auto": 0, "plain": 1, "tiled": 2, "f64acc": 3}
+
+
+class BlipError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class EvalOpts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("tile_pos", ctypes.c_int),
+                ("vec", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libblip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1204_1121_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.blip_load.restype = ci
+    L.blip_load.argtypes = [dp, ci, ci, ci, ci, vp, ci, dp, ctypes.POINTER(vp)]
+    L.blip_eval.restype = ci
+    L.blip_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.blip_eval_ex.restype = ci
+    L.blip_eval_ex.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(EvalOpts), vp]
+    L.blip_table_info.restype = ci
+    L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
+                                  ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.blip_free.restype = ci
+    L.blip_free.argtypes = [vp]
+    L.blip_last_error.restype = ctypes.c_char_p
+    L.blip_last_error.argtypes = []
+    L.blip_version.restype = ctypes.c_char_p
+    L.blip_version.argtypes = []
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != BLIP_OK:
+        raise BlipError(status, lib().blip_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Table:
+    """A coefficient table resident on the current GPU (``blip_load``)."""
+
+    def __init__(self, lattice, n, coef: np.ndarray, storage: str = "f32",
+                 kvec=None):
+        L = lib()
+        n1, n2, n3 = (int(v) for v in n)
+        cplx = storage in ("c64", "cbf16", "cf16")
+        want = np.complex64 if cplx else np.float32
+        coef = np.ascontiguousarray(coef, dtype=want)
+        if coef.ndim != 4 or coef.shape[:3] != (n1, n2, n3):
+            raise ValueError("coef must be [n1, n2, n3, L]")
+        self.norb = int(coef.shape[3])
+        self.complex = cplx
+        self.storage = storage
+        self.n = (n1, n2, n3)
+        self.lattice = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        k = None if kvec is None else np.ascontiguousarray(np.asarray(kvec, np.float64).reshape(3))
+        h = ctypes.c_void_p()
+        check(L.blip_load(_dptr(self.lattice), n1, n2, n3, self.norb,
+                          coef.ctypes.data_as(ctypes.c_void_p), STORAGE[storage],
+                          _dptr(k) if k is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise BlipError(-6, "table already freed")
+        return self._h
+
+    def info(self) -> dict:
+        norb, st = ctypes.c_int(), ctypes.c_int()
+        rb, db = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().blip_table_info(self.handle, ctypes.byref(norb), ctypes.byref(st),
+                                    ctypes.byref(rb), ctypes.byref(db)))
+        return {"norb": norb.value, "storage": st.value, "row_bytes": rb.value,
+                "device_bytes": db.value}
+
+    def alloc_outputs(self, npos: int, grad: bool = True, device=None):
+        """Output tensors [npos, L], [npos, 3, L], [npos, L] (complex64 or float32)."""
+        dt = torch.complex64 if self.complex else torch.float32
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        val = torch.empty((npos, self.norb), dtype=dt, device=dev)
+        if not grad:
+            return val, None, None
+        g = torch.empty((npos, 3, self.norb), dtype=dt, device=dev)
+        lap = torch.empty((npos, self.norb), dtype=dt, device=dev)
+        return val, g, lap
+
+    def eval(self, pos: torch.Tensor, grad: bool = True, out=None, kernel: str = "auto",
+             tile_pos: int = 0, vec: int = 0, stream=None):
+        """Evaluate at positions ``pos`` (cuda float64 [npos, 3]); returns
+        (val, grad, lap) tensors (grad/lap None for values only)."""
+        if pos.dtype != torch.float64 or not pos.is_cuda or not pos.is_contiguous():
+            raise ValueError("pos must be a contiguous float64 CUDA tensor [npos, 3]")
+        npos = pos.shape[0]
+        if out is None:
+            out = self.alloc_outputs(npos, grad, pos.device)
+        val, g, lap = out
+        sp = _stream_ptr(stream)
+        if kernel == "auto" and tile_pos == 0 and vec == 0:
+            check(lib().blip_eval(self.handle, _ptr(pos), npos, _ptr(val), _ptr(g), _ptr(lap), sp))
+        else:
+            o = EvalOpts(KERNEL[kernel], int(tile_pos), int(vec))
+            check(lib().blip_eval_ex(self.handle, _ptr(pos), npos, _ptr(val), _ptr(g), _ptr(lap),
+                                     ctypes.byref(o), sp))
+        return val, g, lap
+
+    def free(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            check(lib().blip_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return lib().blip_version().decode()

@@ -1,0 +1,8 @@
+// Instantiation of the evaluation and quantize launchers for F16 storage.
+#include "blip_launch.hpp"
+
+namespace blip {
+template hipError_t launch_eval<F16>(const KArgs&, const Cfg&, hipStream_t);
+template hipError_t launch_quantize<F16>(const float*, char*, int64_t, int, int64_t, float,
+                                          hipStream_t);
+}  // namespace blip

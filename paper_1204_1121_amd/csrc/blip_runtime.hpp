@@ -1,0 +1,66 @@
+// Internal declarations shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "blip.h"
+#include "blip_launch.hpp"
+
+namespace blip {
+
+constexpr uint32_t kTableMagic = 0xB11F7AB1u;
+
+enum ElemKind { ELEM_F32 = 0, ELEM_BF16 = 1, ELEM_F16 = 2 };
+
+// A tuned launch shape for npos in [lo, hi].
+struct TuneEntry {
+    int64_t lo, hi;
+    int P, OE;
+};
+
+}  // namespace blip
+
+struct blip_table_s {
+    uint32_t magic;
+    int device;
+    double A[9];         // lattice rows a_1, a_2, a_3
+    double G[9];         // A^{-1}
+    double M[9];         // M_cd = n_d G_cd
+    double g6[6];        // g_11, g_22, g_33, g_12, g_13, g_23
+    double k[3];         // k-point (complex tables with a Bloch factor)
+    int n[3];
+    int L;               // orbitals
+    int W;               // table elements per site: L (real) or 2L (complex)
+    blip_dtype storage;
+    int elem;            // blip::ElemKind
+    int esize;           // bytes per table element
+    bool complex_;
+    bool bloch;
+    bool ortho;          // lattice rows along the axes: metric is diagonal
+    int64_t row_bytes;   // W * esize rounded up to 128 bytes
+    int64_t nrows;       // n1 * n2 * n3
+    size_t table_bytes;
+    char* d_table;
+    float out_scale;     // 2^-e for FP16 tables stored as a * 2^e
+    mutable std::mutex tune_mu;
+    std::vector<blip::TuneEntry> tune;
+};
+
+namespace blip {
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail_hip(hipError_t e, const char* what);
+bool aligned16(const void* p);
+bool table_ok(const blip_table_s* t);
+void fill_table_args(const blip_table_s* t, KArgs& a);
+hipError_t dispatch(const blip_table_s* t, const KArgs& a, const Cfg& c, hipStream_t s);
+void choose_shape(const blip_table_s* t, int64_t npos, int& P, int& OE);
+bool valid_oe(const blip_table_s* t, int OE);
+void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t grid, Cfg& c,
+              KArgs& a);
+int upload_table(blip_table_s* t, const void* host);
+
+}  // namespace blip

@@ -1,0 +1,92 @@
+"""The C-ABI library loads, exports every symbol include/blip.h declares, and
+rejects bad arguments on the host before touching a GPU (CPU-only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "blip.h")
+LIB = os.path.join(ROOT, "paper_1204_1121_amd", "libblip.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"BLIP_API\s+[\w\s\*]+?\b(blip_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def blip():
+    import torch  # noqa: F401  (one HIP runtime for the process)
+    from paper_1204_1121_amd import blip as b
+    if not os.path.exists(LIB):
+        from paper_1204_1121_amd import build
+        build.build()
+    return b
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("blip_load", "blip_eval", "blip_eval_ex", "blip_free",
+                     "blip_last_error", "blip_table_info", "blip_version"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(blip):
+    L = blip.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_no_stray_exports(blip):
+    """Only the declared C ABI is visible (everything else is hidden)."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True,
+                         text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert exported <= set(_declared()) | {"_init", "_fini"}, exported - set(_declared())
+
+
+def _load(blip, lattice=None, n=(4, 4, 4), norb=2, storage=0, kvec=None, coef=True):
+    L = blip.lib()
+    A = np.ascontiguousarray(np.eye(3) * 4.0 if lattice is None else lattice, dtype=np.float64)
+    c = np.zeros(max(1, int(np.prod(n)) * max(norb, 1) * 2), dtype=np.float32)
+    h = ctypes.c_void_p()
+    k = None if kvec is None else np.ascontiguousarray(kvec, dtype=np.float64)
+    rc = L.blip_load(A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n[0], n[1], n[2], norb,
+                     c.ctypes.data_as(ctypes.c_void_p) if coef else None, storage,
+                     k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if k is not None else None,
+                     ctypes.byref(h))
+    return rc, h
+
+
+def test_load_argument_errors(blip):
+    assert _load(blip, n=(3, 4, 4))[0] == -1            # grid < 4
+    assert _load(blip, norb=0)[0] == -1                  # no orbitals
+    assert _load(blip, coef=False)[0] == -1              # NULL coefficients
+    assert _load(blip, lattice=np.zeros((3, 3)))[0] == -1   # singular
+    sing = np.array([[1.0, 2, 3], [2, 4, 6], [0, 0, 1]])
+    assert _load(blip, lattice=sing)[0] == -1
+    bad = np.eye(3)
+    bad[1, 1] = np.nan
+    assert _load(blip, lattice=bad)[0] == -1
+    assert _load(blip, storage=9)[0] == -4               # unknown dtype
+    assert _load(blip, storage=0, kvec=[0.1, 0, 0])[0] == -4   # k-point on real table
+    msg = blip.lib().blip_last_error().decode()
+    assert "complex" in msg
+
+
+def test_eval_rejects_bad_handle(blip):
+    L = blip.lib()
+    rc = L.blip_eval(None, None, 0, None, None, None, None)
+    assert rc == -6
+    junk = (ctypes.c_uint32 * 64)()
+    rc = L.blip_eval(ctypes.cast(junk, ctypes.c_void_p), None, 1, None, None, None, None)
+    assert rc == -6
+    assert L.blip_free(None) == 0
+
+
+def test_version_string(blip):
+    assert "gfx950" in blip.version()
