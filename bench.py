@@ -1,0 +1,260 @@
+"""Benchmark of the blip orbital-evaluation hot path on one MI355X.
+
+Workload: the TiO2-supercell-shaped table (18x18x12 bohr cell, 72x72x48
+grid, 768 real orbitals, FP32 coefficients N(0,1)/sqrt(S)) evaluated at
+quasi-simultaneous move blocks of 1,536 positions (Gaussian sigma = 0.5 bohr
+displacements of uniform electron sites, unwrapped).  One step is one
+blip_eval of a whole block: FP64 wrap and split, weights, the 64-row
+gather-accumulate of value, gradient and Laplacian, and the stores.
+Timed steps rotate through 16 independent blocks (different walkers).
+
+Prints ONE JSON line with the metric, the roofline of the evaluation kernel
+(algorithmic bytes per launch / average launch time from HIP events on the
+launch stream), the plain single-block kernel on the same blocks, and the
+FP64 oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "orbital evals/s (val+grad+lap, 768 orbs) & HBM GB/s vs plain; p50/p99 served"
+UNIT = "orbital evals/s"
+HBM_PEAK_GBS = 8000.0
+NROT = 16
+COUNTERS = os.path.join(ROOT, "profiles", "tiled_kernel_tio2_block1536_counters.json")
+KERNEL_SOURCES = ["paper_1204_1121_amd/csrc/blip_device.hpp",
+                  "paper_1204_1121_amd/csrc/blip_launch.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def distinct_rows(lattice, n, pos) -> int:
+    """Exact number of distinct coefficient rows a block touches (the U of
+    the algorithmic byte count): every site of every position's 4x4x4
+    stencil, de-duplicated.  Measurement only."""
+    G = np.linalg.inv(np.asarray(lattice, dtype=np.float64))
+    u = pos @ G
+    u = u - np.floor(u)
+    u[u >= 1.0] = 0.0
+    nn = np.asarray(n, dtype=np.int64)
+    t = u * nn
+    i0 = np.floor(t).astype(np.int64)
+    i0[i0 >= nn] = 0
+    m = np.arange(-1, 3)
+    i1 = (i0[:, 0, None] + m) % nn[0]
+    i2 = (i0[:, 1, None] + m) % nn[1]
+    i3 = (i0[:, 2, None] + m) % nn[2]
+    rows = ((i1[:, :, None, None] * nn[1] + i2[:, None, :, None]) * nn[2]
+            + i3[:, None, None, :])
+    return int(np.unique(rows.reshape(-1)).size)
+
+
+def time_launches(fn, blocks, steps, warmup, stream, pre=None):
+    """Run fn(block) warmup+steps times; returns (wall seconds for the timed
+    steps, per-launch durations in seconds from events on `stream`).
+    ``pre`` (optional) runs before each launch, outside its event pair."""
+    import torch
+    for i in range(warmup):
+        fn(blocks[i % len(blocks)])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if pre is not None:
+            pre()
+        ev[i][0].record(stream)
+        fn(blocks[(warmup + i) % len(blocks)])
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    durs = [a.elapsed_time(b) * 1e-3 for a, b in ev]
+    return wall, durs
+
+
+def cpu_baseline(spec, coef, npos, budget_s=12.0):
+    """FP64 oracle on a bounded sample of the same workload, all host cores:
+    whole move blocks of the benchmark's shape, as many as fit ~budget_s."""
+    import oracle
+    from paper_1204_1121_amd import workloads as wl
+    threads = len(os.sched_getaffinity(0))
+    L = spec.norb
+    # calibrate on one block, then size the sample to ~budget_s
+    first = wl.move_block(spec, npos, block=1000)
+    t0 = time.perf_counter()
+    oracle.evaluate(spec.lattice, spec.n, coef, first, nthreads=threads)
+    dt1 = max(time.perf_counter() - t0, 1e-6)
+    nblk = int(max(1, min(256, budget_s / dt1)))
+    sample = np.concatenate([wl.move_block(spec, npos, block=1000 + b) for b in range(nblk)])
+    t0 = time.perf_counter()
+    oracle.evaluate(spec.lattice, spec.n, coef, sample, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sample.shape[0] * L / dt, "unit": UNIT, "cores": threads,
+            "kind": "oracle",
+            "sample": f"{nblk} move blocks of {npos} positions ({sample.shape[0]} positions "
+                      f"x {L} orbitals, val+grad+lap, FP64): {dt:.1f} s on {threads} threads"}
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size (calibrates rocprof byte counters)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "gbs": 2 * nbytes / dt / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--npos", type=int, default=1536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache measurement (profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (rocprof counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    spec = wl.spec_tio2()
+    t0 = time.perf_counter()
+    coef = wl.coefficients(spec)
+    table = blip.Table(spec.lattice, spec.n, coef, "f32")
+    torch.cuda.synchronize()
+    log(f"table {spec.name}: {table.info()['device_bytes'] / 1e6:.1f} MB resident "
+        f"({time.perf_counter() - t0:.1f} s)")
+
+    npos, L = args.npos, spec.norb
+    blocks_np = [wl.move_block(spec, npos, block=b) for b in range(NROT)]
+    blocks = [torch.from_numpy(b).cuda() for b in blocks_np]
+    out = table.alloc_outputs(npos)
+
+    calls = {id(b): table.bind(b, out) for b in blocks}
+
+    def step(pos):
+        calls[id(pos)]()
+
+    wall, durs = time_launches(step, blocks, args.steps, args.warmup, stream)
+    ms_per_step = wall / args.steps * 1e3
+    value = npos * L * args.steps / wall
+    t_kernel = float(np.mean(durs))
+    log(f"tuned: {ms_per_step * 1e3:.1f} us/step wall, kernel {t_kernel * 1e6:.1f} us "
+        f"(median {np.median(durs) * 1e6:.1f})")
+
+    # algorithmic bytes per launch: distinct rows + outputs + positions
+    row_bytes = L * 4
+    U = [distinct_rows(spec.lattice, spec.n, b) for b in blocks_np]
+    b_alg = [u * row_bytes + npos * 5 * L * 4 + 24 * npos for u in U]
+    b_alg_mean = float(np.mean(b_alg))
+    b_gather = 64 * npos * row_bytes + npos * 5 * L * 4 + 24 * npos
+    achieved = b_alg_mean / t_kernel / 1e9
+
+    traffic = None
+    try:
+        with open(COUNTERS) as f:
+            cnt = json.load(f)
+        if cnt.get("kernel_source_hash") == kernel_source_hash() and cnt.get("npos") == npos:
+            traffic = cnt.get("hbm_bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+
+    result = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"tio2_72x72x48_L768_block{npos}", "grid": list(spec.n),
+                   "cell_bohr": [18.0, 18.0, 12.0], "norb": L, "npos": npos,
+                   "storage": "f32", "accumulate": "f32", "wrap": "f64",
+                   "outputs": "val+grad+lap", "rotating_blocks": NROT,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernel_us": {"mean": t_kernel * 1e6, "median": float(np.median(durs)) * 1e6,
+                      "p99": float(np.percentile(durs, 99)) * 1e6},
+        "bytes_per_launch": {"algorithmic": b_alg_mean, "gather_no_reuse": b_gather,
+                             "distinct_rows": float(np.mean(U))},
+    }
+
+    if not args.no_plain:
+        def plain_step(pos):
+            table.eval(pos, out=out, kernel="plain")
+        wall_p, durs_p = time_launches(plain_step, blocks, args.steps, args.warmup, stream)
+        tp = float(np.mean(durs_p))
+        result["plain"] = {"value": npos * L * args.steps / wall_p,
+                           "kernel_us": tp * 1e6,
+                           "hbm_gbs": b_alg_mean / tp / 1e9,
+                           "speedup_tuned_vs_plain": tp / t_kernel}
+        log(f"plain: kernel {tp * 1e6:.1f} us")
+
+    if not args.no_cold:
+        # Cold Infinity Cache: read 1 GiB of unrelated data before every
+        # launch (outside its event pair) so no table row survives from the
+        # previous launch.  Reads leave the cache clean, so the launch pays
+        # no write-back of the sweep.  The main figure keeps the natural
+        # cache state of back-to-back blocks.
+        sweep = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+        sink = torch.empty((), dtype=torch.float32, device="cuda")
+        _, durs_c = time_launches(step, blocks, min(args.steps, 50), 2, stream,
+                                  pre=lambda: torch.sum(sweep, out=sink))
+        tc = float(np.mean(durs_c))
+        result["cold_cache"] = {"kernel_us": tc * 1e6, "hbm_gbs": b_alg_mean / tc / 1e9,
+                                "frac": b_alg_mean / tc / 1e9 / HBM_PEAK_GBS}
+        log(f"cold-cache: kernel {tc * 1e6:.1f} us")
+        del sweep
+
+    if args.copy_probe:
+        result["copy_probe"] = copy_probe()
+
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        result["cpu_baseline"] = cpu_baseline(spec, coef, npos)
+
+    table.free()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,8 +78,9 @@ typedef enum {
                                mapping (Sec. III.B) written for wave64         */
     BLIP_KERNEL_TILED = 2,  /* P positions per workgroup, separable 1-D weights,
                                o orbitals per lane with wide loads             */
-    BLIP_KERNEL_F64ACC = 3  /* tiled kernel with FP64 accumulation (debug;
-                               real FP32 tables only)                          */
+    BLIP_KERNEL_F64ACC = 3  /* tiled kernel with FP64 weights, accumulation and
+                               outputs (debug; real FP32 tables only): val, grad
+                               and lap are double arrays of the same shapes    */
 } blip_kernel;
 
 typedef struct {

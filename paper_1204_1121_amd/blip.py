@@ -127,9 +127,10 @@ class Table:
         return {"norb": norb.value, "storage": st.value, "row_bytes": rb.value,
                 "device_bytes": db.value}
 
-    def alloc_outputs(self, npos: int, grad: bool = True, device=None):
-        """Output tensors [npos, L], [npos, 3, L], [npos, L] (complex64 or float32)."""
-        dt = torch.complex64 if self.complex else torch.float32
+    def alloc_outputs(self, npos: int, grad: bool = True, device=None, f64: bool = False):
+        """Output tensors [npos, L], [npos, 3, L], [npos, L]: complex64 or
+        float32 (float64 for the FP64-accumulate debug kernel)."""
+        dt = torch.complex64 if self.complex else (torch.float64 if f64 else torch.float32)
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         val = torch.empty((npos, self.norb), dtype=dt, device=dev)
         if not grad:
@@ -146,7 +147,7 @@ class Table:
             raise ValueError("pos must be a contiguous float64 CUDA tensor [npos, 3]")
         npos = pos.shape[0]
         if out is None:
-            out = self.alloc_outputs(npos, grad, pos.device)
+            out = self.alloc_outputs(npos, grad, pos.device, f64=(kernel == "f64acc"))
         val, g, lap = out
         sp = _stream_ptr(stream)
         if kernel == "auto" and tile_pos == 0 and vec == 0:
@@ -156,6 +157,23 @@ class Table:
             check(lib().blip_eval_ex(self.handle, _ptr(pos), npos, _ptr(val), _ptr(g), _ptr(lap),
                                      ctypes.byref(o), sp))
         return val, g, lap
+
+    def bind(self, pos: torch.Tensor, out, stream=None):
+        """A zero-argument callable that runs ``blip_eval`` on fixed buffers
+        with the ctypes arguments built once (low host overhead per call)."""
+        if pos.dtype != torch.float64 or not pos.is_cuda or not pos.is_contiguous():
+            raise ValueError("pos must be a contiguous float64 CUDA tensor [npos, 3]")
+        val, g, lap = out
+        fn = lib().blip_eval
+        args = (self.handle, _ptr(pos), ctypes.c_int64(pos.shape[0]), _ptr(val), _ptr(g),
+                _ptr(lap), _stream_ptr(stream))
+        err = lib().blip_last_error
+
+        def call():
+            rc = fn(*args)
+            if rc != BLIP_OK:
+                raise BlipError(rc, err().decode())
+        return call
 
     def free(self) -> None:
         if getattr(self, "_h", None) is not None:

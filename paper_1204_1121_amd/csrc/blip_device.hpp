@@ -58,9 +58,9 @@ struct KArgs {
     int64_t npos;
     const int* perm;         // optional: slot -> original position index
     const int64_t* dev_count;// optional: device-side npos (persistent launch)
-    float* val;              // [npos][W]
-    float* grad;             // [npos][3][W]
-    float* lap;              // [npos][W]
+    void* val;               // [npos][W] float (double for FP64 accumulation)
+    void* grad;              // [npos][3][W]
+    void* lap;               // [npos][W]
 };
 
 // Per-position data prepared in LDS.
@@ -376,16 +376,16 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ cptr,
 template <bool FULL, bool ORTHO, class ACC, int OE>
 __device__ __forceinline__ void finish_cartesian(const KArgs& a,
                                                  ACC (&acc)[NOut<FULL, ORTHO>::value][OE],
-                                                 float (&res)[5][OE])
+                                                 ACC (&res)[5][OE])
 {
 #pragma unroll
     for (int e = 0; e < OE; ++e) {
-        res[0][e] = (float)acc[0][e];
+        res[0][e] = acc[0][e];
         if constexpr (FULL && ORTHO) {
-            res[1][e] = (float)acc[1][e];
-            res[2][e] = (float)acc[2][e];
-            res[3][e] = (float)acc[3][e];
-            res[4][e] = (float)acc[4][e];
+            res[1][e] = acc[1][e];
+            res[2][e] = acc[2][e];
+            res[3][e] = acc[3][e];
+            res[4][e] = acc[4][e];
         } else if constexpr (FULL) {
             const ACC d1 = acc[1][e], d2 = acc[2][e], d3 = acc[3][e];
 #pragma unroll
@@ -393,7 +393,7 @@ __device__ __forceinline__ void finish_cartesian(const KArgs& a,
                 ACC gc = (ACC)a.M[c * 3 + 0] * d1;
                 gc = fma_((ACC)a.M[c * 3 + 1], d2, gc);
                 gc = fma_((ACC)a.M[c * 3 + 2], d3, gc);
-                res[1 + c][e] = (float)gc;
+                res[1 + c][e] = gc;
             }
             ACC l = (ACC)a.g[0] * acc[4][e];
             l = fma_((ACC)a.g[1], acc[5][e], l);
@@ -401,7 +401,7 @@ __device__ __forceinline__ void finish_cartesian(const KArgs& a,
             l = fma_((ACC)(2.0 * a.g[3]), acc[7][e], l);
             l = fma_((ACC)(2.0 * a.g[4]), acc[8][e], l);
             l = fma_((ACC)(2.0 * a.g[5]), acc[9][e], l);
-            res[4][e] = (float)l;
+            res[4][e] = l;
         }
     }
 }
@@ -445,8 +445,9 @@ __device__ __forceinline__ void apply_bloch(const KArgs& a, float cph, float sph
     }
 }
 
-// Store o consecutive floats at p (vector stores when allowed, else masked
-// element stores against the row length W).
+// Store o consecutive outputs at p (vector stores when allowed, else masked
+// element stores against the row length W).  Outputs are float, or double
+// for the FP64-accumulate debug kernel.
 template <int OE>
 __device__ __forceinline__ void store_elems(float* p, const float (&v)[OE], int e0,
                                             int W, bool vec)
@@ -466,6 +467,15 @@ __device__ __forceinline__ void store_elems(float* p, const float (&v)[OE], int 
         for (int i = 0; i < OE; ++i)
             if (e0 + i < W) p[i] = v[i];
     }
+}
+
+template <int OE>
+__device__ __forceinline__ void store_elems(double* p, const double (&v)[OE], int e0,
+                                            int W, bool)
+{
+#pragma unroll
+    for (int i = 0; i < OE; ++i)
+        if (e0 + i < W) p[i] = v[i];
 }
 
 // Workgroup index -> tile index that keeps consecutive tiles on one XCD.
@@ -547,7 +557,7 @@ tiled_kernel(const KArgs a)
             const char* cptr = a.coef + (int64_t)e_ld * E::bytes;
             ACC acc[NO][OE];
             gather_item<E, OE, FULL, ORTHO, ACC>(cptr, a.row_bytes, prep[p], acc);
-            float res[5][OE];
+            ACC res[5][OE];
             finish_cartesian<FULL, ORTHO, ACC, OE>(a, acc, res);
             if constexpr (__is_same(E, F16)) {
 #pragma unroll
@@ -562,17 +572,18 @@ tiled_kernel(const KArgs a)
 #pragma unroll
                 for (int q = 0; q < 5; ++q)
 #pragma unroll
-                    for (int e = 0; e < OE; ++e) res[q][e] = __builtin_nanf("");
+                    for (int e = 0; e < OE; ++e) res[q][e] = (ACC)__builtin_nan("");
             }
             if (lane_ok) {
                 const bool vec = a.vec_store != 0;
-                store_elems<OE>(a.val + jo * W + e0, res[0], e0, W, vec);
+                ACC* val = static_cast<ACC*>(a.val);
+                store_elems<OE>(val + jo * W + e0, res[0], e0, W, vec);
                 if constexpr (FULL) {
-                    float* gbase = a.grad + jo * 3 * W + e0;
+                    ACC* gbase = static_cast<ACC*>(a.grad) + jo * 3 * W + e0;
                     store_elems<OE>(gbase, res[1], e0, W, vec);
                     store_elems<OE>(gbase + W, res[2], e0, W, vec);
                     store_elems<OE>(gbase + 2 * W, res[3], e0, W, vec);
-                    store_elems<OE>(a.lap + jo * W + e0, res[4], e0, W, vec);
+                    store_elems<OE>(static_cast<ACC*>(a.lap) + jo * W + e0, res[4], e0, W, vec);
                 }
             }
         }
@@ -676,12 +687,15 @@ plain_kernel(const KArgs a)
         if (s_bad)
             for (int q = 0; q < 5; ++q)
                 for (int e = 0; e < G; ++e) res[q][e] = __builtin_nanf("");
+        float* val = static_cast<float*>(a.val);
+        float* grad = static_cast<float*>(a.grad);
+        float* lap = static_cast<float*>(a.lap);
         for (int e = 0; e < G; ++e) {
             if (e0 + e >= W) break;
-            a.val[j * W + e0 + e] = res[0][e];
+            val[j * W + e0 + e] = res[0][e];
             if constexpr (FULL) {
-                for (int c = 0; c < 3; ++c) a.grad[(j * 3 + c) * W + e0 + e] = res[1 + c][e];
-                a.lap[j * W + e0 + e] = res[4][e];
+                for (int c = 0; c < 3; ++c) grad[(j * 3 + c) * W + e0 + e] = res[1 + c][e];
+                lap[j * W + e0 + e] = res[4][e];
             }
         }
     }

@@ -30,7 +30,8 @@ namespace detail {
 template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC>
 hipError_t go_tiled(const KArgs& a, const Cfg& c, hipStream_t s)
 {
-    if constexpr (BLOCH && (OE % 2 != 0)) {
+    if constexpr (BLOCH && ((OE % 2 != 0) || !__is_same(ACC, float))) {
+        // the Bloch factor needs whole complex pairs per lane and FP32 outputs
         return hipErrorInvalidValue;
     } else {
         hipLaunchKernelGGL((tiled_kernel<E, OE, FULL, ORTHO, BLOCH, ACC>), dim3(c.grid),

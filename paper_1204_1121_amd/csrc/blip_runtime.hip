@@ -103,13 +103,14 @@ hipError_t dispatch(const blip_table_s* t, const KArgs& a, const Cfg& c, hipStre
 // Default launch shape when the table has not been tuned for this size.
 static void default_shape(const blip_table_s* t, int64_t npos, int& P, int& OE)
 {
-    OE = (t->esize == 4) ? 4 : 8;
-    if (t->bloch && OE < 2) OE = 2;
-    // keep >= ~2 workgroups per CU in flight for mid-size blocks, larger
-    // tiles (more reuse between nearby positions) for big batches
-    if (npos <= 4096) P = 1;
-    else if (npos <= 16384) P = 4;
-    else P = 16;
+    // Measured on MI355X for the 768-orbital FP32 table: 8-byte lane loads
+    // (two table elements) keep ~80 VGPRs and 5 waves/SIMD, and one or two
+    // positions per workgroup fill all 256 CUs in a single wave of
+    // workgroups for blocks of a few thousand positions.
+    OE = (t->esize == 4) ? 2 : 4;
+    if (npos <= 512) P = 1;
+    else if (npos <= 8192) P = 2;
+    else P = 4;
 }
 
 void choose_shape(const blip_table_s* t, int64_t npos, int& P, int& OE)
@@ -204,9 +205,9 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
     fill_table_args(t, a);
     a.pos = pos;
     a.npos = npos;
-    a.val = static_cast<float*>(val);
-    a.grad = static_cast<float*>(grad);
-    a.lap = static_cast<float*>(lap);
+    a.val = val;
+    a.grad = grad;
+    a.lap = lap;
     Cfg c;
     const int64_t ntiles = (npos + P - 1) / P;
     a.ntiles = (int)ntiles;
