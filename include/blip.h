@@ -127,8 +127,9 @@ BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3,
  *  grad  device [npos][3][L]; lap device [npos][L].  Pass both or neither:
  *        grad == lap == NULL runs the values-only kernel.
  *  stream hipStream_t (as void*), NULL = null stream.
- * pos, val, grad and lap must be 16-byte aligned (BLIP_E_ALIGN); the caller
- * owns them and keeps them alive until the stream has run the work.
+ * pos must be 8-byte and val/grad/lap 4-byte aligned (BLIP_E_ALIGN); outputs
+ * whose base addresses are 16-byte aligned get whole-vector stores.  The
+ * caller owns them and keeps them alive until the stream has run the work.
  * Runs the tuned tiled kernel.  No allocation, no synchronisation.
  */
 BLIP_API int blip_eval(blip_table t, const double* pos, int64_t npos,
@@ -146,6 +147,78 @@ BLIP_API int blip_eval(blip_table t, const double* pos, int64_t npos,
 BLIP_API int blip_eval_ex(blip_table t, const double* pos, int64_t npos,
                           void* val, void* grad, void* lap,
                           const blip_eval_opts* opts, void* stream);
+
+/*
+ * blip_eval_batched -- evaluate the move blocks of many walkers in one
+ * persistent launch (quasi-simultaneous updating makes every moved electron
+ * of every walker an independent evaluation, Sec. III.A, Eq. (11.12.23.1)).
+ *
+ *  pos       device double[capacity][3]: the walkers' blocks concatenated;
+ *            walker w owns rows offsets[w] .. offsets[w+1]-1.
+ *  offsets   device int64[nw+1], offsets[0] == 0, non-decreasing.  Only
+ *            offsets[nw] (the total) is read, on the device, so the host
+ *            need not know it; a total above capacity is clamped to capacity.
+ *  nw        number of walkers (0: nothing is enqueued).
+ *  capacity  host bound on the total: the size of pos and of the outputs.
+ *  val, grad, lap  as blip_eval, with capacity rows; row j belongs to the
+ *            same position as pos row j.  Rows past the total are untouched.
+ *  workspace device scratch of at least blip_workspace_size(t, capacity)
+ *            bytes, 256-byte aligned, owned by the caller; calls that share
+ *            a workspace must be ordered on one stream.
+ * The positions are sorted by space on the device (counting sort by brick of
+ * cells) so that positions sharing stencil rows are evaluated together; each
+ * output is still computed in the fixed order of blip_eval, so results equal
+ * the per-walker blip_eval results bit for bit.  Enqueues five kernels on the
+ * stream; no allocation, no synchronisation, and no memset (capturable).
+ */
+BLIP_API int blip_eval_batched(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                               int64_t capacity, void* val, void* grad, void* lap,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* blip_workspace_size -- bytes of workspace blip_eval_batched needs for a
+ * batch of up to `capacity` positions on table t. */
+BLIP_API int blip_workspace_size(blip_table t, int64_t capacity, size_t* bytes);
+
+/*
+ * Plans: blip_eval_batched captured once into a HIP graph on fixed buffers,
+ * then replayed with one hipGraphLaunch.  Between launches the caller may
+ * rewrite the contents of pos and offsets (the device-side total may change
+ * from launch to launch up to capacity); the buffers themselves must stay
+ * alive until blip_plan_free.  The launch shape is fixed at creation.
+ */
+typedef struct blip_plan_s* blip_plan;
+BLIP_API int blip_plan_create(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                              int64_t capacity, void* val, void* grad, void* lap,
+                              void* workspace, size_t workspace_bytes, blip_plan* out);
+BLIP_API int blip_plan_launch(blip_plan p, void* stream);
+BLIP_API int blip_plan_free(blip_plan p);
+
+/*
+ * blip_autotune -- time every launch shape (P positions per workgroup x o
+ * table elements per lane) on the caller's buffers and keep the fastest for
+ * this table and this size bucket (npos in [2^k, 2^(k+1))).  offsets == NULL
+ * tunes blip_eval on pos[npos] (P in {1,2,4,8}); otherwise it tunes
+ * blip_eval_batched with capacity npos (P in {8,16,32,64}).  o runs over
+ * {1,2,4} (FP32 storage) or {2,4,8} (16-bit storage).  Synchronous: it
+ * synchronises the stream after each timed launch.  The outputs are
+ * overwritten.  results (may be NULL) receives up to max_results timings;
+ * best receives the winner.
+ */
+typedef struct {
+    int tile_pos;   /* P */
+    int vec;        /* o */
+    double us;      /* median launch time, microseconds */
+} blip_tune_result;
+BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                           int64_t npos, void* val, void* grad, void* lap, void* workspace,
+                           size_t workspace_bytes, void* stream, blip_tune_result* results,
+                           int max_results, int* n_results, blip_tune_result* best);
+
+/* blip_set_shape / blip_get_shape -- set or read the launch shape used for
+ * npos's size bucket (batched != 0: the batched path), e.g. to restore a
+ * cached autotuning result. */
+BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec);
+BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec);
 
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */

@@ -38,6 +38,10 @@ class EvalOpts(ctypes.Structure):
                 ("vec", ctypes.c_int)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_pos", ctypes.c_int), ("vec", ctypes.c_int), ("us", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -58,6 +62,25 @@ def lib() -> ctypes.CDLL:
     L.blip_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.blip_eval_ex.restype = ci
     L.blip_eval_ex.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(EvalOpts), vp]
+    L.blip_eval_batched.restype = ci
+    L.blip_eval_batched.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.blip_workspace_size.restype = ci
+    L.blip_workspace_size.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.blip_plan_create.restype = ci
+    L.blip_plan_create.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp, ctypes.c_size_t,
+                                   ctypes.POINTER(vp)]
+    L.blip_plan_launch.restype = ci
+    L.blip_plan_launch.argtypes = [vp, vp]
+    L.blip_plan_free.restype = ci
+    L.blip_plan_free.argtypes = [vp]
+    L.blip_autotune.restype = ci
+    L.blip_autotune.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp, ctypes.c_size_t, vp,
+                                ctypes.POINTER(TuneResult), ci, ctypes.POINTER(ci),
+                                ctypes.POINTER(TuneResult)]
+    L.blip_set_shape.restype = ci
+    L.blip_set_shape.argtypes = [vp, ci, i64, ci, ci]
+    L.blip_get_shape.restype = ci
+    L.blip_get_shape.argtypes = [vp, ci, i64, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -175,10 +198,107 @@ class Table:
                 raise BlipError(rc, err().decode())
         return call
 
+    # -- batched walker blocks -------------------------------------------
+
+    def workspace_bytes(self, capacity: int) -> int:
+        n = ctypes.c_size_t()
+        check(lib().blip_workspace_size(self.handle, int(capacity), ctypes.byref(n)))
+        return int(n.value)
+
+    def workspace(self, capacity: int, device=None) -> torch.Tensor:
+        """Device scratch for blip_eval_batched (torch allocations are 256-B aligned)."""
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        return torch.empty(max(1, self.workspace_bytes(capacity)), dtype=torch.uint8, device=dev)
+
+    def eval_batched(self, pos: torch.Tensor, offsets: torch.Tensor, grad: bool = True,
+                     out=None, workspace=None, capacity: int | None = None, stream=None):
+        """Evaluate concatenated walker blocks; offsets is a cuda int64
+        tensor [nw+1].  Returns (val, grad, lap) with ``capacity`` rows."""
+        if offsets.dtype != torch.int64 or not offsets.is_cuda:
+            raise ValueError("offsets must be a CUDA int64 tensor [nw+1]")
+        cap = pos.shape[0] if capacity is None else int(capacity)
+        if out is None:
+            out = self.alloc_outputs(cap, grad, pos.device)
+        if workspace is None:
+            workspace = self.workspace(cap, pos.device)
+        val, g, lap = out
+        check(lib().blip_eval_batched(self.handle, _ptr(pos), _ptr(offsets),
+                                      int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
+                                      _ptr(lap), _ptr(workspace), workspace.numel(),
+                                      _stream_ptr(stream)))
+        return val, g, lap
+
+    def plan(self, pos, offsets, out, workspace, capacity: int | None = None) -> "Plan":
+        return Plan(self, pos, offsets, out, workspace, capacity)
+
+    def autotune(self, pos, out, offsets=None, workspace=None, capacity: int | None = None,
+                 stream=None):
+        """Time every (P, o) and keep the fastest for this size bucket.
+        Returns (best, all) as dicts {tile_pos, vec, us}."""
+        val, g, lap = out
+        res = (TuneResult * 32)()
+        n = ctypes.c_int()
+        best = TuneResult()
+        if offsets is None:
+            check(lib().blip_autotune(self.handle, _ptr(pos), None, 0, pos.shape[0], _ptr(val),
+                                      _ptr(g), _ptr(lap), None, 0, _stream_ptr(stream), res, 32,
+                                      ctypes.byref(n), ctypes.byref(best)))
+        else:
+            cap = pos.shape[0] if capacity is None else int(capacity)
+            if workspace is None:
+                workspace = self.workspace(cap, pos.device)
+            check(lib().blip_autotune(self.handle, _ptr(pos), _ptr(offsets),
+                                      int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
+                                      _ptr(lap), _ptr(workspace), workspace.numel(),
+                                      _stream_ptr(stream), res, 32, ctypes.byref(n),
+                                      ctypes.byref(best)))
+        conv = lambda r: {"tile_pos": r.tile_pos, "vec": r.vec, "us": r.us}
+        return conv(best), [conv(res[i]) for i in range(n.value)]
+
+    def set_shape(self, npos: int, tile_pos: int, vec: int, batched: bool = False) -> None:
+        check(lib().blip_set_shape(self.handle, int(batched), int(npos), int(tile_pos), int(vec)))
+
+    def get_shape(self, npos: int, batched: bool = False):
+        P, o = ctypes.c_int(), ctypes.c_int()
+        check(lib().blip_get_shape(self.handle, int(batched), int(npos), ctypes.byref(P),
+                                   ctypes.byref(o)))
+        return P.value, o.value
+
     def free(self) -> None:
         if getattr(self, "_h", None) is not None:
             check(lib().blip_free(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Plan:
+    """blip_eval_batched captured into a HIP graph on fixed buffers."""
+
+    def __init__(self, table: Table, pos, offsets, out, workspace, capacity=None):
+        cap = pos.shape[0] if capacity is None else int(capacity)
+        val, g, lap = out
+        h = ctypes.c_void_p()
+        check(lib().blip_plan_create(table.handle, _ptr(pos), _ptr(offsets),
+                                     int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
+                                     _ptr(lap), _ptr(workspace), workspace.numel(),
+                                     ctypes.byref(h)))
+        self._h = h
+        # keep the captured buffers alive as long as the plan
+        self._keep = (table, pos, offsets, out, workspace)
+
+    def launch(self, stream=None) -> None:
+        check(lib().blip_plan_launch(self._h, _stream_ptr(stream)))
+
+    def free(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            check(lib().blip_plan_free(self._h))
+            self._h = None
+            self._keep = None
 
     def __del__(self):
         try:

@@ -1,0 +1,405 @@
+// Batched evaluation of ragged walker blocks (one persistent launch over a
+// spatially sorted batch), hipGraph plans of that sequence, and the
+// launch-shape autotuner.
+//
+// Quasi-simultaneous updating makes every moved electron of every walker an
+// independent evaluation against the same table (Sec. III.A, Eq.
+// (11.12.23.1)), so a batch of walker blocks is evaluated as one
+// concatenated set of positions; the offsets only delimit walkers for the
+// caller.  Sorting the concatenation by space lets positions that share
+// stencil rows run together, so shared rows are fetched from HBM once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "blip_runtime.hpp"
+
+namespace blip {
+// Spatial sort of a position batch (counting sort by brick).
+//
+// Positions are binned by the 4x4x4-cell brick (coarser if the grid is very
+// large) that holds their cell index i0, with bricks numbered in Morton
+// (Z-curve) order so that consecutive bins are spatial neighbours.  The
+// evaluation then walks positions in bin order: a tile of P positions covers
+// one or two bricks, whose stencils share most of their rows.
+struct SortArgs {
+    int bshift;              // brick edge = 2^bshift cells
+    int mbits;               // Morton bits per dimension
+    int nbins;               // 2^(3 mbits)
+    int* counts;             // [nbins + 1]
+    int* cursor;             // [nbins]
+    int* keys;               // [capacity]
+    int* perm;               // [capacity]
+};
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    // bits b of v -> bit 3b
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+__device__ __forceinline__ int64_t batch_count(const KArgs& a)
+{
+    int64_t n = *a.dev_count;
+    if (n > a.npos) n = a.npos;   // never beyond the buffers' capacity
+    if (n < 0) n = 0;
+    return n;
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void bin_kernel(const KArgs a, SortArgs s)
+{
+    const int64_t n = batch_count(a);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double* rp = a.pos + 3 * j;
+        double r[3] = {rp[0], rp[1], rp[2]};
+        bool bad = false;
+        int i0[3];
+        double f[3];
+        wrap_split(a, r, i0, f, bad);
+        const uint32_t bx = (uint32_t)i0[0] >> s.bshift, by = (uint32_t)i0[1] >> s.bshift,
+                       bz = (uint32_t)i0[2] >> s.bshift;
+        const int key = (int)((spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz));
+        s.keys[j] = key;
+        atomicAdd(&s.counts[key], 1);
+    }
+}
+
+// Exclusive scan of counts[0..nbins) into cursor (one workgroup of 1024).
+__global__ void __launch_bounds__(1024) scan_kernel(SortArgs s)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (s.nbins + 1023) / 1024;
+    const int b0 = t * per;
+    int sum = 0;
+    for (int i = 0; i < per && b0 + i < s.nbins; ++i) sum += s.counts[b0 + i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;   // exclusive prefix of this thread's range
+    for (int i = 0; i < per && b0 + i < s.nbins; ++i) {
+        s.cursor[b0 + i] = run;
+        run += s.counts[b0 + i];
+    }
+}
+
+__global__ void scatter_kernel(const KArgs a, SortArgs s)
+{
+    const int64_t n = batch_count(a);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = atomicAdd(&s.cursor[s.keys[j]], 1);
+        s.perm[slot] = (int)j;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+struct SortLayout {
+    int bshift, mbits, nbins;
+    size_t off_counts, off_cursor, off_keys, off_perm, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static SortLayout sort_layout(const blip_table_s* t, int64_t capacity)
+{
+    SortLayout L{};
+    int bshift = 2;
+    auto nb = [&](int sh) {
+        int m = 0;
+        for (int d = 0; d < 3; ++d) m = std::max(m, ((t->n[d] - 1) >> sh) + 1);
+        return m;
+    };
+    while (nb(bshift) > 64) ++bshift;
+    int mbits = 1;
+    while ((1 << mbits) < nb(bshift)) ++mbits;
+    L.bshift = bshift;
+    L.mbits = mbits;
+    L.nbins = 1 << (3 * mbits);
+    size_t off = 0;
+    L.off_counts = off;
+    off = align256(off + sizeof(int) * (size_t)(L.nbins + 1));
+    L.off_cursor = off;
+    off = align256(off + sizeof(int) * (size_t)L.nbins);
+    L.off_keys = off;
+    off = align256(off + sizeof(int) * (size_t)std::max<int64_t>(capacity, 1));
+    L.off_perm = off;
+    off = align256(off + sizeof(int) * (size_t)std::max<int64_t>(capacity, 1));
+    L.total = off;
+    return L;
+}
+
+static int check_batched_args(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                              int64_t capacity, void* val, void* grad, void* lap,
+                              void* workspace, size_t ws_bytes)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (nw < 0) return fail(BLIP_E_ARG, "nw must be >= 0 (got %d)", nw);
+    if (capacity < 0) return fail(BLIP_E_ARG, "capacity must be >= 0");
+    if (nw == 0 || capacity == 0) return BLIP_OK;
+    if (offsets == nullptr) return fail(BLIP_E_ARG, "offsets must be non-NULL");
+    if ((reinterpret_cast<uintptr_t>(offsets) & 7u) != 0)
+        return fail(BLIP_E_ALIGN, "offsets must be 8-byte aligned");
+    int rc = check_eval_args(t, pos, capacity, val, grad, lap);
+    if (rc != BLIP_OK) return rc;
+    const SortLayout L = sort_layout(t, capacity);
+    if (workspace == nullptr || ws_bytes < L.total)
+        return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", L.total, ws_bytes);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return fail(BLIP_E_ALIGN, "workspace must be 256-byte aligned");
+    return BLIP_OK;
+}
+
+static int grid_blocks(int64_t n, int per, int cap)
+{
+    int64_t g = (n + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Enqueue fill -> bin -> scan -> scatter -> persistent evaluation on s.
+static int enqueue_batched(const blip_table_s* t, const double* pos, const int64_t* offsets,
+                           int nw, int64_t capacity, void* val, void* grad, void* lap,
+                           void* workspace, int P, int OE, hipStream_t s)
+{
+    const SortLayout L = sort_layout(t, capacity);
+    char* ws = static_cast<char*>(workspace);
+    SortArgs sa;
+    sa.bshift = L.bshift;
+    sa.mbits = L.mbits;
+    sa.nbins = L.nbins;
+    sa.counts = reinterpret_cast<int*>(ws + L.off_counts);
+    sa.cursor = reinterpret_cast<int*>(ws + L.off_cursor);
+    sa.keys = reinterpret_cast<int*>(ws + L.off_keys);
+    sa.perm = reinterpret_cast<int*>(ws + L.off_perm);
+    KArgs a;
+    fill_table_args(t, a);
+    a.pos = pos;
+    a.npos = capacity;
+    a.dev_count = offsets + nw;
+
+    // counts are cleared by a kernel, not hipMemsetAsync, so the sequence
+    // can be captured into a graph and replayed
+    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_blocks(L.nbins + 1, 256, 1024)), dim3(256), 0, s,
+                       sa.counts, L.nbins + 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "fill kernel");
+    const int g = grid_blocks(capacity, 256, 2048);
+    hipLaunchKernelGGL(bin_kernel, dim3(g), dim3(256), 0, s, a, sa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "bin kernel");
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "scan kernel");
+    hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, s, a, sa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "scatter kernel");
+    // persistent grid: about four workgroups per CU, never more than tiles
+    const int grid = grid_blocks(capacity, P, 4 * std::max(1, t->ncu));
+    return launch_tiled(t, pos, capacity, val, grad, lap, KIND_TILED, P, OE, sa.perm,
+                        offsets + nw, grid, true, s);
+}
+
+static int batched_shape(const blip_table_s* t, int64_t capacity, int& P, int& OE)
+{
+    choose_shape(t, MODE_BATCHED, capacity, P, OE);
+    return BLIP_OK;
+}
+
+}  // namespace blip
+
+struct blip_plan_s {
+    uint32_t magic;
+    blip_table table;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+using namespace blip;
+
+static constexpr uint32_t kPlanMagic = 0xB11F91A4u;
+
+extern "C" {
+
+BLIP_API int blip_workspace_size(blip_table t, int64_t capacity, size_t* bytes)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (capacity < 0 || bytes == nullptr) return fail(BLIP_E_ARG, "bad capacity or NULL bytes");
+    *bytes = sort_layout(t, capacity).total;
+    return BLIP_OK;
+}
+
+BLIP_API int blip_eval_batched(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                               int64_t capacity, void* val, void* grad, void* lap,
+                               void* workspace, size_t workspace_bytes, void* stream)
+{
+    int rc = check_batched_args(t, pos, offsets, nw, capacity, val, grad, lap, workspace,
+                                workspace_bytes);
+    if (rc != BLIP_OK || nw == 0 || capacity == 0) return rc;
+    int P, OE;
+    batched_shape(t, capacity, P, OE);
+    return enqueue_batched(t, pos, offsets, nw, capacity, val, grad, lap, workspace, P, OE,
+                           static_cast<hipStream_t>(stream));
+}
+
+BLIP_API int blip_plan_create(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                              int64_t capacity, void* val, void* grad, void* lap,
+                              void* workspace, size_t workspace_bytes, blip_plan* out)
+{
+    if (out == nullptr) return fail(BLIP_E_ARG, "out must be non-NULL");
+    *out = nullptr;
+    int rc = check_batched_args(t, pos, offsets, nw, capacity, val, grad, lap, workspace,
+                                workspace_bytes);
+    if (rc != BLIP_OK) return rc;
+    if (nw == 0 || capacity == 0) return fail(BLIP_E_ARG, "a plan needs nw > 0 and capacity > 0");
+    int P, OE;
+    batched_shape(t, capacity, P, OE);
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return fail_hip(e, "hipStreamBeginCapture");
+    }
+    rc = enqueue_batched(t, pos, offsets, nw, capacity, val, grad, lap, workspace, P, OE, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc != BLIP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail_hip(e, "hipGraphInstantiate");
+    }
+    auto* p = new blip_plan_s{kPlanMagic, t, g, x};
+    *out = p;
+    return BLIP_OK;
+}
+
+BLIP_API int blip_plan_launch(blip_plan p, void* stream)
+{
+    if (p == nullptr || p->magic != kPlanMagic) return fail(BLIP_E_STATE, "invalid plan handle");
+    if (!table_ok(p->table)) return fail(BLIP_E_STATE, "the plan's table has been freed");
+    hipError_t e = hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    return BLIP_OK;
+}
+
+BLIP_API int blip_plan_free(blip_plan p)
+{
+    if (p == nullptr) return BLIP_OK;
+    if (p->magic != kPlanMagic) return fail(BLIP_E_STATE, "invalid plan handle");
+    hipError_t e1 = hipGraphExecDestroy(p->exec);
+    hipError_t e2 = hipGraphDestroy(p->graph);
+    p->magic = 0;
+    delete p;
+    if (e1 != hipSuccess) return fail_hip(e1, "hipGraphExecDestroy");
+    if (e2 != hipSuccess) return fail_hip(e2, "hipGraphDestroy");
+    return BLIP_OK;
+}
+
+BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                           int64_t npos, void* val, void* grad, void* lap, void* workspace,
+                           size_t workspace_bytes, void* stream, blip_tune_result* results,
+                           int max_results, int* n_results, blip_tune_result* best)
+{
+    const bool batched = offsets != nullptr;
+    int rc = batched ? check_batched_args(t, pos, offsets, nw, npos, val, grad, lap, workspace,
+                                          workspace_bytes)
+                     : check_eval_args(t, pos, npos, val, grad, lap);
+    if (rc != BLIP_OK) return rc;
+    if (npos == 0 || (batched && nw == 0)) return fail(BLIP_E_ARG, "nothing to tune (npos == 0)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int> Ps = batched ? std::vector<int>{8, 16, 32, 64} : std::vector<int>{1, 2, 4, 8};
+    std::vector<int> Os = t->esize == 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{2, 4, 8};
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return fail_hip(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    blip_tune_result top{0, 0, 1e30};
+    int nres = 0;
+    for (int P : Ps) {
+        for (int OE : Os) {
+            if (!valid_oe(t, OE)) continue;
+            std::vector<float> ts;
+            for (int it = 0; it < 9 && rc == BLIP_OK; ++it) {
+                (void)hipEventRecord(e0, s);
+                rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap, workspace,
+                                               P, OE, s)
+                             : launch_tiled(t, pos, npos, val, grad, lap, KIND_TILED, P, OE,
+                                            nullptr, nullptr, 0, false, s);
+                (void)hipEventRecord(e1, s);
+                e = hipEventSynchronize(e1);
+                if (e != hipSuccess) rc = fail_hip(e, "autotune sync");
+                float ms = 0.0f;
+                if (rc == BLIP_OK && it >= 2) {
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ts.push_back(ms);
+                }
+            }
+            if (rc != BLIP_OK) break;
+            std::sort(ts.begin(), ts.end());
+            const double us = ts[ts.size() / 2] * 1e3;
+            if (results && nres < max_results) results[nres] = blip_tune_result{P, OE, us};
+            ++nres;
+            if (us < top.us) top = blip_tune_result{P, OE, us};
+        }
+        if (rc != BLIP_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != BLIP_OK) return rc;
+    set_tuned(t, batched ? MODE_BATCHED : MODE_BLOCK, npos, top.tile_pos, top.vec);
+    if (n_results) *n_results = std::min(nres, max_results);
+    if (best) *best = top;
+    return BLIP_OK;
+}
+
+BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (tile_pos < 1 || tile_pos > kMaxTile) return fail(BLIP_E_ARG, "tile_pos must be 1..%d", kMaxTile);
+    if (!valid_oe(t, vec)) return fail(BLIP_E_ARG, "vec=%d not supported for this table", vec);
+    if (npos < 1) return fail(BLIP_E_ARG, "npos must be >= 1");
+    set_tuned(t, batched ? MODE_BATCHED : MODE_BLOCK, npos, tile_pos, vec);
+    return BLIP_OK;
+}
+
+BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    int P, OE;
+    choose_shape(t, batched ? MODE_BATCHED : MODE_BLOCK, npos, P, OE);
+    if (tile_pos) *tile_pos = P;
+    if (vec) *vec = OE;
+    return BLIP_OK;
+}
+
+}  // extern "C"

@@ -49,6 +49,7 @@ struct KArgs {
     int P;                   // positions per tile
     int ntiles;              // ceil(npos / P)
     int vec_store;           // 1 if W % o == 0 (whole-vector stores allowed)
+    int chunk_major;         // item order within a tile: chunk-major if 1
     double G[9];             // A^{-1}
     double M[9];             // M_cd = n_d G_cd  (d t_d / d r_c)
     double g[6];             // g_11, g_22, g_33, g_12, g_13, g_23 (g = M^T M)
@@ -545,8 +546,17 @@ tiled_kernel(const KArgs a)
 
         const int items = np * C;
         for (int item = wave; item < items; item += nwaves) {
-            const int p = item / C;
-            const int ch = item - p * C;
+            // chunk-major order: the wavefronts of a workgroup work on the
+            // same orbital chunk of neighbouring positions at the same time,
+            // so rows that spatially sorted positions share are hit in L1/L2
+            int p, ch;
+            if (a.chunk_major) {
+                ch = item / np;
+                p = item - ch * np;
+            } else {
+                p = item / C;
+                ch = item - p * C;
+            }
             const int64_t slot = j0 + p;
             const int64_t jo = a.perm ? (int64_t)a.perm[slot] : slot;
             const int e0 = (ch * kWave + lane) * OE;
@@ -727,5 +737,6 @@ __global__ void quantize_kernel(const float* __restrict__ src, char* __restrict_
         else *d = __builtin_bit_cast(uint16_t, (_Float16)(v * scale));
     }
 }
+
 
 }  // namespace blip

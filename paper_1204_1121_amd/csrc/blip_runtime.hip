@@ -101,23 +101,36 @@ hipError_t dispatch(const blip_table_s* t, const KArgs& a, const Cfg& c, hipStre
 }
 
 // Default launch shape when the table has not been tuned for this size.
-static void default_shape(const blip_table_s* t, int64_t npos, int& P, int& OE)
+static void default_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
 {
     // Measured on MI355X for the 768-orbital FP32 table: 8-byte lane loads
     // (two table elements) keep ~80 VGPRs and 5 waves/SIMD, and one or two
     // positions per workgroup fill all 256 CUs in a single wave of
-    // workgroups for blocks of a few thousand positions.
+    // workgroups for blocks of a few thousand positions.  Sorted batches use
+    // larger tiles so neighbouring positions share rows in L1/L2.
     OE = (t->esize == 4) ? 2 : 4;
+    if (mode == MODE_BATCHED) {
+        P = 16;
+        return;
+    }
     if (npos <= 512) P = 1;
     else if (npos <= 8192) P = 2;
     else P = 4;
 }
 
-void choose_shape(const blip_table_s* t, int64_t npos, int& P, int& OE)
+// Tuned entries cover the power-of-two bucket [2^k, 2^(k+1)) holding npos.
+static void bucket(int64_t npos, int64_t& lo, int64_t& hi)
+{
+    lo = 1;
+    while (lo * 2 <= npos) lo *= 2;
+    hi = lo * 2 - 1;
+}
+
+void choose_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
 {
     {
         std::lock_guard<std::mutex> lk(t->tune_mu);
-        for (const TuneEntry& e : t->tune) {
+        for (const TuneEntry& e : t->tune[mode]) {
             if (npos >= e.lo && npos <= e.hi) {
                 P = e.P;
                 OE = e.OE;
@@ -125,7 +138,23 @@ void choose_shape(const blip_table_s* t, int64_t npos, int& P, int& OE)
             }
         }
     }
-    default_shape(t, npos, P, OE);
+    default_shape(t, mode, npos, P, OE);
+}
+
+void set_tuned(blip_table_s* t, int mode, int64_t npos, int P, int OE)
+{
+    int64_t lo, hi;
+    bucket(npos, lo, hi);
+    std::lock_guard<std::mutex> lk(t->tune_mu);
+    auto& v = t->tune[mode];
+    for (TuneEntry& e : v) {
+        if (e.lo == lo) {
+            e.P = P;
+            e.OE = OE;
+            return;
+        }
+    }
+    v.push_back(TuneEntry{lo, hi, P, OE});
 }
 
 bool valid_oe(const blip_table_s* t, int OE)
@@ -145,7 +174,12 @@ void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t
     const int chunk_elems = kWave * OE;
     a.chunks = (t->W + chunk_elems - 1) / chunk_elems;
     a.P = P;
-    a.vec_store = (t->W % OE == 0) ? 1 : 0;
+    // whole-vector stores need every row start aligned to the vector size
+    const uintptr_t vb = (uintptr_t)std::min(16, OE * 4);
+    const bool outs_aligned =
+        ((reinterpret_cast<uintptr_t>(a.val) | reinterpret_cast<uintptr_t>(a.grad) |
+          reinterpret_cast<uintptr_t>(a.lap)) & (vb - 1)) == 0;
+    a.vec_store = (t->W % OE == 0 && outs_aligned) ? 1 : 0;
     c.kind = kind;
     c.OE = OE;
     const int items = P * a.chunks;
@@ -156,15 +190,60 @@ void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t
     c.bloch = t->bloch;
 }
 
-int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
-                void* lap, const blip_eval_opts* opts, void* stream)
+int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
+                 void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
+                 int grid, bool chunk_major, hipStream_t s)
+{
+    KArgs a;
+    fill_table_args(t, a);
+    a.pos = pos;
+    a.npos = npos;
+    a.val = val;
+    a.grad = grad;
+    a.lap = lap;
+    a.perm = perm;
+    a.dev_count = dev_count;
+    a.chunk_major = chunk_major ? 1 : 0;
+    const int64_t ntiles = (npos + P - 1) / P;
+    a.ntiles = (int)ntiles;
+    Cfg c;
+    make_cfg(t, kind, P, OE, grad != nullptr, dev_count ? grid : ntiles, c, a);
+    hipError_t e = dispatch(t, a, c, s);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return BLIP_OK;
+}
+
+int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
+                    void* lap)
 {
     if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
     if (npos < 0) return fail(BLIP_E_ARG, "npos must be >= 0 (got %lld)", (long long)npos);
     if ((grad == nullptr) != (lap == nullptr))
         return fail(BLIP_E_ARG, "pass both grad and lap, or neither (values only)");
+    if (npos == 0) return BLIP_OK;
+    if (npos > (int64_t)INT32_MAX)
+        return fail(BLIP_E_ARG, "npos too large (%lld)", (long long)npos);
+    if (pos == nullptr || val == nullptr)
+        return fail(BLIP_E_ARG, "pos and val must be non-NULL when npos > 0");
+    auto al = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & (m - 1)) == 0; };
+    if (!al(pos, 8)) return fail(BLIP_E_ALIGN, "pos must be 8-byte aligned");
+    if (!al(val, 4) || (grad && !al(grad, 4)) || (lap && !al(lap, 4)))
+        return fail(BLIP_E_ALIGN, "val, grad and lap must be 4-byte aligned");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != t->device)
+        return fail(BLIP_E_STATE, "table lives on device %d but device %d is current", t->device,
+                    dev);
+    return BLIP_OK;
+}
+
+int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
+                void* lap, const blip_eval_opts* opts, void* stream)
+{
     int kind = KIND_TILED, P = 0, OE = 0;
     if (opts) {
+        if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
         if (opts->kernel < BLIP_KERNEL_AUTO || opts->kernel > BLIP_KERNEL_F64ACC)
             return fail(BLIP_E_ARG, "unknown kernel %d", opts->kernel);
         if (opts->kernel == BLIP_KERNEL_PLAIN) kind = KIND_PLAIN;
@@ -182,39 +261,30 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
         if (kind == KIND_F64ACC && OE == 8)
             return fail(BLIP_E_ARG, "vec=8 not supported by the FP64-accumulate kernel");
     }
-    if (npos == 0) return BLIP_OK;
-    if (npos > (int64_t)INT32_MAX)
-        return fail(BLIP_E_ARG, "npos too large (%lld)", (long long)npos);
-    if (pos == nullptr || val == nullptr)
-        return fail(BLIP_E_ARG, "pos and val must be non-NULL when npos > 0");
-    if (!aligned16(pos) || !aligned16(val) || (grad && !aligned16(grad)) || (lap && !aligned16(lap)))
-        return fail(BLIP_E_ALIGN, "pos, val, grad and lap must be 16-byte aligned");
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-    if (dev != t->device)
-        return fail(BLIP_E_STATE, "table lives on device %d but device %d is current", t->device, dev);
+    int rc = check_eval_args(t, pos, npos, val, grad, lap);
+    if (rc != BLIP_OK || npos == 0) return rc;
 
     int P0 = 0, OE0 = 0;
-    choose_shape(t, npos, P0, OE0);
+    choose_shape(t, MODE_BLOCK, npos, P0, OE0);
     if (P == 0) P = P0;
     if (OE == 0) OE = OE0;
     if (kind == KIND_F64ACC && OE > 4) OE = 4;
-
-    KArgs a;
-    fill_table_args(t, a);
-    a.pos = pos;
-    a.npos = npos;
-    a.val = val;
-    a.grad = grad;
-    a.lap = lap;
-    Cfg c;
-    const int64_t ntiles = (npos + P - 1) / P;
-    a.ntiles = (int)ntiles;
-    make_cfg(t, kind, P, OE, grad != nullptr, ntiles, c, a);
-    e = dispatch(t, a, c, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return fail_hip(e, "kernel launch");
-    return BLIP_OK;
+    if (kind == KIND_PLAIN) {
+        KArgs a;
+        fill_table_args(t, a);
+        a.pos = pos;
+        a.npos = npos;
+        a.val = val;
+        a.grad = grad;
+        a.lap = lap;
+        Cfg c;
+        make_cfg(t, kind, 1, 1, grad != nullptr, npos, c, a);
+        hipError_t e = dispatch(t, a, c, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return fail_hip(e, "kernel launch");
+        return BLIP_OK;
+    }
+    return launch_tiled(t, pos, npos, val, grad, lap, kind, P, OE, nullptr, nullptr, 0, false,
+                        static_cast<hipStream_t>(stream));
 }
 
 }  // namespace blip
@@ -269,6 +339,7 @@ BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3, int norb
     auto* t = new blip_table_s();
     t->magic = kTableMagic;
     t->device = dev;
+    t->ncu = prop.multiProcessorCount;
     std::memcpy(t->A, lattice, sizeof t->A);
     std::memcpy(t->G, G, sizeof t->G);
     t->n[0] = n1;

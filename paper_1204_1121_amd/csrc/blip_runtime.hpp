@@ -21,11 +21,15 @@ struct TuneEntry {
     int P, OE;
 };
 
+// Launch-shape tables kept per table: single blocks, and sorted batches.
+enum TuneMode { MODE_BLOCK = 0, MODE_BATCHED = 1 };
+
 }  // namespace blip
 
 struct blip_table_s {
     uint32_t magic;
     int device;
+    int ncu;             // compute units of the device
     double A[9];         // lattice rows a_1, a_2, a_3
     double G[9];         // A^{-1}
     double M[9];         // M_cd = n_d G_cd
@@ -46,7 +50,7 @@ struct blip_table_s {
     char* d_table;
     float out_scale;     // 2^-e for FP16 tables stored as a * 2^e
     mutable std::mutex tune_mu;
-    std::vector<blip::TuneEntry> tune;
+    std::vector<blip::TuneEntry> tune[2];   // indexed by blip::TuneMode
 };
 
 namespace blip {
@@ -57,8 +61,16 @@ bool aligned16(const void* p);
 bool table_ok(const blip_table_s* t);
 void fill_table_args(const blip_table_s* t, KArgs& a);
 hipError_t dispatch(const blip_table_s* t, const KArgs& a, const Cfg& c, hipStream_t s);
-void choose_shape(const blip_table_s* t, int64_t npos, int& P, int& OE);
+void choose_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE);
+void set_tuned(blip_table_s* t, int mode, int64_t npos, int P, int OE);
+// Launch the tiled (or FP64-accumulate) kernel.  perm/dev_count select the
+// sorted persistent form used for batches; grid is then the workgroup count.
+int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
+                 void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
+                 int grid, bool chunk_major, hipStream_t s);
 bool valid_oe(const blip_table_s* t, int OE);
+int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
+                    void* lap);
 void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t grid, Cfg& c,
               KArgs& a);
 int upload_table(blip_table_s* t, const void* host);

@@ -1,0 +1,182 @@
+"""Batched walker blocks: one persistent launch over a spatially sorted batch,
+hipGraph plans and the autotuner, checked against per-walker blip_eval
+(bit for bit) and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1204_1121_amd import workloads as wl
+from tests.gpu_util import group_errors, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def blip():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    from paper_1204_1121_amd import blip as b
+    b.lib()
+    return b
+
+
+@pytest.fixture(scope="module")
+def small(blip):
+    rng = np.random.default_rng(31)
+    A = np.diag([7.0, 6.0, 5.0])
+    n = (28, 24, 20)
+    L = 300
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    t = blip.Table(A, n, c, "f32")
+    yield A, n, c, t
+    t.free()
+
+
+def ragged(rng, A, nw, maxb, sigma=0.3):
+    sizes = rng.integers(1, maxb + 1, nw)
+    off = np.zeros(nw + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    sites = rng.uniform(0, 1, (int(off[-1]), 3)) @ A
+    return sites + rng.normal(0, sigma, sites.shape), off
+
+
+def np_out(o):
+    return {"val": to_np(o[0]), "grad": to_np(o[1]), "lap": to_np(o[2])}
+
+
+def test_batched_equals_per_walker(blip, small):
+    A, n, c, t = small
+    rng = np.random.default_rng(1)
+    pos, off = ragged(rng, A, 40, 30)
+    say(f"batched: 40 walkers, {off[-1]} positions")
+    p = torch.from_numpy(pos).cuda()
+    o = torch.from_numpy(off).cuda()
+    yb = np_out(t.eval_batched(p, o))
+    torch.cuda.synchronize()
+    for w in range(40):
+        a, b = int(off[w]), int(off[w + 1])
+        yw = np_out(t.eval(p[a:b].contiguous()))
+        for k in yb:
+            np.testing.assert_array_equal(yb[k][a:b], yw[k], err_msg=f"walker {w} {k}")
+    ref = oracle.evaluate(A, n, c, pos, nthreads=8)
+    e = group_errors(yb, ref)
+    say("  vs oracle: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    assert max(e.values()) <= FP32_TOL
+
+
+def test_batched_every_shape_bitwise(blip, small):
+    A, n, c, t = small
+    rng = np.random.default_rng(2)
+    pos, off = ragged(rng, A, 64, 50)
+    p = torch.from_numpy(pos).cuda()
+    o = torch.from_numpy(off).cuda()
+    say(f"batched shapes: {off[-1]} positions")
+    base = np_out(t.eval(p))
+    ws = t.workspace(pos.shape[0])
+    for P in (1, 8, 16, 32, 64):
+        for vec in (1, 2, 4):
+            t.set_shape(pos.shape[0], P, vec, batched=True)
+            y = np_out(t.eval_batched(p, o, workspace=ws))
+            for k in y:
+                np.testing.assert_array_equal(y[k], base[k], err_msg=f"P={P} o={vec} {k}")
+
+
+def test_batched_total_below_capacity(blip, small):
+    """Rows past the device-side total are not written; nw = 0 is a no-op."""
+    A, n, c, t = small
+    rng = np.random.default_rng(3)
+    pos, off = ragged(rng, A, 10, 20)
+    cap = int(off[-1]) + 37
+    pfull = np.concatenate([pos, np.full((37, 3), 1.0)])
+    p = torch.from_numpy(pfull).cuda()
+    o = torch.from_numpy(off).cuda()
+    out = t.alloc_outputs(cap)
+    for x in out:
+        x.fill_(12345.0)
+    say("batched: total below capacity")
+    y = np_out(t.eval_batched(p, o, out=out, capacity=cap))
+    tot = int(off[-1])
+    for k in y:
+        assert np.all(y[k][tot:] == 12345.0), k
+        assert np.all(y[k][:tot] != 12345.0), k
+    # nw == 0 enqueues nothing
+    t.eval_batched(p, torch.zeros(1, dtype=torch.int64, device="cuda"), out=out, capacity=cap)
+    torch.cuda.synchronize()
+    assert np.all(to_np(out[0])[tot:] == 12345.0)
+
+
+def test_plan_replays_match_eager(blip, small):
+    """A captured plan replayed with new positions and totals each time
+    (eager torch work and synchronisations between replays) equals the
+    eager batched call on the same inputs, every replay."""
+    A, n, c, t = small
+    rng = np.random.default_rng(4)
+    cap = 2000
+    p = torch.zeros((cap, 3), dtype=torch.float64, device="cuda")
+    o = torch.zeros(33, dtype=torch.int64, device="cuda")
+    out = t.alloc_outputs(cap)
+    ws = t.workspace(cap)
+    plan = t.plan(p, o, out, ws, capacity=cap)
+    say("plan replays")
+    for rep in range(5):
+        pos, off = ragged(rng, A, 32, 60)
+        assert off[-1] <= cap
+        p[: pos.shape[0]].copy_(torch.from_numpy(pos))
+        o.copy_(torch.from_numpy(off))
+        junk = torch.randn(1 << 20, device="cuda").sum()      # unrelated eager work
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        got = {k: v[: pos.shape[0]].copy() for k, v in np_out(out).items()}
+        ref = np_out(t.eval(torch.from_numpy(pos).cuda()))
+        for k in got:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"replay {rep} {k}")
+        del junk
+    plan.free()
+
+
+def test_autotune(blip, small):
+    A, n, c, t = small
+    rng = np.random.default_rng(5)
+    pos, off = ragged(rng, A, 50, 40)
+    p = torch.from_numpy(pos).cuda()
+    o = torch.from_numpy(off).cuda()
+    out = t.alloc_outputs(pos.shape[0])
+    say("autotune block and batched")
+    best, allr = t.autotune(p, out)
+    assert len(allr) == 12 and best in allr
+    assert t.get_shape(pos.shape[0]) == (best["tile_pos"], best["vec"])
+    best_b, allb = t.autotune(p, out, offsets=o)
+    assert len(allb) == 12 and best_b in allb
+    assert t.get_shape(pos.shape[0], batched=True) == (best_b["tile_pos"], best_b["vec"])
+    ref = np_out(t.eval(p))
+    y = np_out(t.eval_batched(p, o))
+    for k in y:
+        np.testing.assert_array_equal(y[k], ref[k])
+
+
+def test_tio2_512_walkers(blip):
+    """The batched workload: 512 walkers, blocks of U[1,256] positions on the
+    72x72x48 x 768 table; bitwise equal to one blip_eval of the
+    concatenation, and a sample against the oracle."""
+    spec = wl.spec_tio2()
+    say("TiO2 table for the 512-walker batch")
+    c = wl.coefficients(spec)
+    t = blip.Table(spec.lattice, spec.n, c, "f32")
+    b = wl.walker_batch(spec, nwalkers=512, max_block=256)
+    say(f"  {b.pos.shape[0]} positions")
+    p = torch.from_numpy(b.pos).cuda()
+    o = torch.from_numpy(b.offsets).cuda()
+    yb = np_out(t.eval_batched(p, o))
+    ye = np_out(t.eval(p))
+    for k in yb:
+        np.testing.assert_array_equal(yb[k], ye[k])
+    idx = np.random.default_rng(0).choice(b.pos.shape[0], 512, replace=False)
+    ref = oracle.evaluate(spec.lattice, spec.n, c, b.pos[idx], nthreads=8)
+    e = group_errors({k: v[idx] for k, v in yb.items()}, ref)
+    say("  sample vs oracle: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    assert max(e.values()) <= FP32_TOL
+    t.free()
