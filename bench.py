@@ -115,6 +115,134 @@ def cpu_baseline(spec, coef, npos, budget_s=12.0):
                       f"x {L} orbitals, val+grad+lap, FP64): {dt:.1f} s on {threads} threads"}
 
 
+def bench_batched(table, spec, args, nbatch=4):
+    """512 walkers with move blocks of U[1,256] positions on the same table:
+    one sorted persistent launch per batch (replayed hipGraph plan), against
+    the plain kernel on the concatenation and per-walker launch loops."""
+    import torch
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    bs = [wl.walker_batch(spec, nwalkers=512, max_block=256, batch=q) for q in range(nbatch)]
+    cap = max(b.pos.shape[0] for b in bs)
+    L = spec.norb
+    pos = [torch.from_numpy(b.pos).cuda() for b in bs]
+    off = [torch.from_numpy(b.offsets).cuda() for b in bs]
+    out = table.alloc_outputs(cap)
+    ws = table.workspace(cap)
+    best, allr = table.autotune(pos[0], out, offsets=off[0], workspace=ws, capacity=cap)
+    log(f"batched autotune: P={best['tile_pos']} o={best['vec']} ({best['us']:.0f} us)")
+    plans = [table.plan(p, o, out, ws, capacity=p.shape[0]) for p, o in zip(pos, off)]
+    steps = max(10, min(args.steps, 50))
+    wall, durs = time_launches(lambda i: plans[i].launch(), list(range(nbatch)), steps, 3, stream)
+    npos_mean = float(np.mean([b.pos.shape[0] for b in bs]))
+    t_b = float(np.mean(durs))
+    U = [distinct_rows(spec.lattice, spec.n, b.pos) for b in bs]
+    b_alg = float(np.mean([u * L * 4 + b.pos.shape[0] * (5 * L * 4 + 24) for u, b in zip(U, bs)]))
+    res = {"walkers": 512, "positions_mean": npos_mean, "tuned": best, "autotune": allr,
+           "value": npos_mean * L * steps / wall, "unit": UNIT,
+           "launch_us": t_b * 1e6, "hbm_gbs": b_alg / t_b / 1e9,
+           "frac": b_alg / t_b / 1e9 / HBM_PEAK_GBS, "bytes_algorithmic": b_alg,
+           "flops_per_launch": npos_mean * L * 296 * 2}
+    res["tflops"] = res["flops_per_launch"] / t_b / 1e12
+
+    def plain_all(i):
+        table.eval(pos[i], out=tuple(x[: pos[i].shape[0]] for x in out), kernel="plain")
+    _, dp = time_launches(plain_all, list(range(nbatch)), 10, 2, stream)
+    res["plain_concatenated_us"] = float(np.mean(dp)) * 1e6
+
+    def unsorted_all(i):
+        table.eval(pos[i], out=tuple(x[: pos[i].shape[0]] for x in out))
+    _, du = time_launches(unsorted_all, list(range(nbatch)), 10, 2, stream)
+    res["tiled_unsorted_us"] = float(np.mean(du)) * 1e6
+    views = [[(pos[q][int(b.offsets[w]):int(b.offsets[w + 1])],
+               tuple(x[int(b.offsets[w]):int(b.offsets[w + 1])] for x in out))
+              for w in range(512)] for q, b in enumerate(bs)]
+
+    def per_walker(kernel):
+        def f(i):
+            for pw, ow in views[i]:
+                table.eval(pw, out=ow, kernel=kernel)
+        return f
+    _, dpw = time_launches(per_walker("plain"), list(range(nbatch)), 3, 1, stream)
+    res["per_walker_plain_us"] = float(np.mean(dpw)) * 1e6
+    res["speedup_vs_per_walker_plain"] = res["per_walker_plain_us"] / res["launch_us"]
+    res["speedup_vs_plain_concatenated"] = res["plain_concatenated_us"] / res["launch_us"]
+    for pl in plans:
+        pl.free()
+    log(f"batched: {t_b * 1e6:.0f} us per 512-walker batch; plain(concat) "
+        f"{res['plain_concatenated_us']:.0f} us; per-walker plain loop {res['per_walker_plain_us']:.0f} us")
+    return res
+
+
+def bench_serving(args):
+    """Three resident systems (the 768-orbital table; 48^3 x 256; 96x96x64 x
+    1024), requests of 1..1536 positions (log-uniform) arriving by Poisson
+    process at rates swept around the saturated rate; continuous batching
+    with HBM-budget admission.  Latency from the scheduled arrival."""
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+    from paper_1204_1121_amd.serve import GpuBackend, Server, ServeRequest
+    specs = wl.spec_serving()
+    t0 = time.perf_counter()
+    tables = []
+    for sp in specs:
+        c = wl.coefficients(sp)
+        tables.append(blip.Table(sp.lattice, sp.n, c, "f32"))
+        del c
+    resident = sum(t.info()["device_bytes"] for t in tables)
+    log(f"serving: {len(tables)} tables, {resident / 1e9:.2f} GB resident "
+        f"({time.perf_counter() - t0:.1f} s)")
+    norb = [sp.norb for sp in specs]
+    nreq = args.serve_requests
+
+    def make(rate, seed, n=nreq):
+        rq = wl.serving_requests(len(specs), n, rate=rate, specs=specs, seed=seed)
+        return [ServeRequest(r.rid, r.system, r.pos, arrival=r.arrival) for r in rq]
+
+    def run(backend, budget, reqs):
+        sv = Server(backend, budget_bytes=budget)
+        st = sv.run(reqs)
+        ev = sum(r.npos * norb[r.system] for r in reqs if r.status == "done")
+        st["evals_per_s"] = ev / st["makespan_s"]
+        return st
+
+    out = {"tables_gb": resident / 1e9, "requests_per_point": nreq}
+    be = GpuBackend(tables, capacity=16384, max_requests=512, batched=True)
+    run(be, 2 << 30, make(1e9, 99, 500))                     # warm-up
+    sat = run(be, 2 << 30, make(1e9, 100))                   # all at t=0: saturated
+    out["saturated"] = sat
+    rate_sat = sat["req_per_s"]
+    log(f"serving saturated: {rate_sat:.0f} req/s, {sat['evals_per_s']:.3e} evals/s")
+    sweep = []
+    for f in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+        st = run(be, 2 << 30, make(f * rate_sat, 200 + int(f * 100)))
+        st["offered_fraction"] = f
+        st["offered_req_per_s"] = f * rate_sat
+        sweep.append(st)
+        log(f"  rate {f:.2f}x: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+            f"{st['evals_per_s']:.3e} evals/s")
+    out["sweep"] = sweep
+    small = run(be, 64 << 20, make(0.9 * rate_sat, 300))
+    small["budget_bytes"] = 64 << 20
+    out["small_budget_0.9x"] = small
+    be.close()
+    # unbatched baseline: one request per launch, plain single-block kernel
+    bp = GpuBackend(tables, batched=False, kernel="plain")
+    run(bp, 2 << 30, make(1e9, 99, 200))
+    psat = run(bp, 2 << 30, make(1e9, 101, max(1000, nreq // 5)))
+    out["plain_unbatched_saturated"] = psat
+    pl = run(bp, 2 << 30, make(0.5 * psat["req_per_s"], 301, max(1000, nreq // 5)))
+    pl["offered_req_per_s"] = 0.5 * psat["req_per_s"]
+    out["plain_unbatched_0.5x_of_its_saturation"] = pl
+    log(f"plain unbatched saturated: {psat['req_per_s']:.0f} req/s, "
+        f"{psat['evals_per_s']:.3e} evals/s")
+    bp.close()
+    for t in tables:
+        t.free()
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=5):
     """A plain device copy of known size (calibrates rocprof byte counters)."""
     import torch
@@ -139,6 +267,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache measurement (profiling runs)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-walker batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per serving rate point")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (rocprof counter calibration)")
     args = ap.parse_args()
@@ -171,6 +303,10 @@ def main():
     blocks = [torch.from_numpy(b).cuda() for b in blocks_np]
     out = table.alloc_outputs(npos)
 
+    # pick the launch shape for this block size with the library's autotuner
+    # (setup, outside the timed region)
+    best, _ = table.autotune(blocks[0], out)
+    log(f"autotuned block shape: P={best['tile_pos']} o={best['vec']} ({best['us']:.1f} us)")
     calls = {id(b): table.bind(b, out) for b in blocks}
 
     def step(pos):
@@ -238,12 +374,25 @@ def main():
         sweep = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
         sink = torch.empty((), dtype=torch.float32, device="cuda")
         _, durs_c = time_launches(step, blocks, min(args.steps, 50), 2, stream,
-                                  pre=lambda: torch.sum(sweep, out=sink))
+                                  pre=lambda: torch.sum(sweep, dim=0, out=sink))
         tc = float(np.mean(durs_c))
         result["cold_cache"] = {"kernel_us": tc * 1e6, "hbm_gbs": b_alg_mean / tc / 1e9,
                                 "frac": b_alg_mean / tc / 1e9 / HBM_PEAK_GBS}
         log(f"cold-cache: kernel {tc * 1e6:.1f} us")
         del sweep
+
+    if not args.no_batched:
+        try:
+            result["batched"] = bench_batched(table, spec, args)
+        except Exception as e:            # recorded, never fatal for the main line
+            result["batched"] = {"error": f"{type(e).__name__}: {e}"}
+    table.free()
+
+    if not args.no_serving:
+        try:
+            result["serving"] = bench_serving(args)
+        except Exception as e:
+            result["serving"] = {"error": f"{type(e).__name__}: {e}"}
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe()
@@ -251,8 +400,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         result["cpu_baseline"] = cpu_baseline(spec, coef, npos)
+    del coef
 
-    table.free()
     print(json.dumps(result), flush=True)
 
 

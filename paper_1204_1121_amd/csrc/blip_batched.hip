@@ -19,28 +19,23 @@
 namespace blip {
 // Spatial sort of a position batch (counting sort by brick).
 //
-// Positions are binned by the 4x4x4-cell brick (coarser if the grid is very
-// large) that holds their cell index i0, with bricks numbered in Morton
-// (Z-curve) order so that consecutive bins are spatial neighbours.  The
-// evaluation then walks positions in bin order: a tile of P positions covers
-// one or two bricks, whose stencils share most of their rows.
+// Positions are binned by the brick of cells that holds their cell index
+// i0; bricks are numbered by their rank along a Morton curve (a table built
+// at load), so consecutive bins are spatial neighbours.  The evaluation then
+// walks positions in bin order: a tile of P positions covers one or two
+// bricks, whose stencils share most of their rows.
 struct SortArgs {
     int bshift;              // brick edge = 2^bshift cells
-    int mbits;               // Morton bits per dimension
-    int nbins;               // 2^(3 mbits)
-    int* counts;             // [nbins + 1]
+    int nb1, nb2;            // bricks along a_2, a_3
+    int nbins;               // number of bricks (<= 16384)
+    const int* rank;         // [nb0][nb1][nb2] -> Morton rank
+    int* counts;             // [nbins] then 8 per-XCD tile counters
     int* cursor;             // [nbins]
     int* keys;               // [capacity]
     int* perm;               // [capacity]
 };
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v)
-{
-    // bits b of v -> bit 3b
-    uint32_t r = 0;
-    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
-    return r;
-}
+constexpr int kMaxBins = 16384;
 
 __device__ __forceinline__ int64_t batch_count(const KArgs& a)
 {
@@ -66,36 +61,55 @@ __global__ void bin_kernel(const KArgs a, SortArgs s)
         int i0[3];
         double f[3];
         wrap_split(a, r, i0, f, bad);
-        const uint32_t bx = (uint32_t)i0[0] >> s.bshift, by = (uint32_t)i0[1] >> s.bshift,
-                       bz = (uint32_t)i0[2] >> s.bshift;
-        const int key = (int)((spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz));
+        const int bx = i0[0] >> s.bshift, by = i0[1] >> s.bshift, bz = i0[2] >> s.bshift;
+        const int key = s.rank[(bx * s.nb1 + by) * s.nb2 + bz];
         s.keys[j] = key;
         atomicAdd(&s.counts[key], 1);
     }
 }
 
-// Exclusive scan of counts[0..nbins) into cursor (one workgroup of 1024).
+// Exclusive scan of counts[0..nbins) into cursor: one workgroup of 1024,
+// counts staged in LDS, wave-level shuffles for the partial sums.
 __global__ void __launch_bounds__(1024) scan_kernel(SortArgs s)
 {
-    __shared__ int part[1024];
+    __shared__ int sh[kMaxBins];
+    __shared__ int wsum[16];
     const int t = threadIdx.x;
-    const int per = (s.nbins + 1023) / 1024;
+    const int nb = s.nbins;
+    for (int i = t; i < nb; i += 1024) sh[i] = s.counts[i];
+    __syncthreads();
+    const int per = (nb + 1023) / 1024;
     const int b0 = t * per;
     int sum = 0;
-    for (int i = 0; i < per && b0 + i < s.nbins; ++i) sum += s.counts[b0 + i];
-    part[t] = sum;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < nb) sum += sh[b0 + i];
+    const int lane = t & 63, w = t >> 6;
+    int v = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) wsum[w] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = (t >= off) ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    if (w == 0) {
+        int x = lane < 16 ? wsum[lane] : 0;
+        for (int off = 1; off < 16; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane < 16) wsum[lane] = x;
     }
-    int run = part[t] - sum;   // exclusive prefix of this thread's range
-    for (int i = 0; i < per && b0 + i < s.nbins; ++i) {
-        s.cursor[b0 + i] = run;
-        run += s.counts[b0 + i];
+    __syncthreads();
+    int run = v - sum + (w > 0 ? wsum[w - 1] : 0);
+    for (int i = 0; i < per; ++i) {
+        if (b0 + i < nb) {
+            const int c = sh[b0 + i];
+            sh[b0 + i] = run;
+            run += c;
+        }
     }
+    __syncthreads();
+    for (int i = t; i < nb; i += 1024) s.cursor[i] = sh[i];
 }
 
 __global__ void scatter_kernel(const KArgs a, SortArgs s)
@@ -113,7 +127,7 @@ __global__ void scatter_kernel(const KArgs a, SortArgs s)
 // Host side.
 
 struct SortLayout {
-    int bshift, mbits, nbins;
+    int nbins;
     size_t off_counts, off_cursor, off_keys, off_perm, total;
 };
 
@@ -122,21 +136,10 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 static SortLayout sort_layout(const blip_table_s* t, int64_t capacity)
 {
     SortLayout L{};
-    int bshift = 2;
-    auto nb = [&](int sh) {
-        int m = 0;
-        for (int d = 0; d < 3; ++d) m = std::max(m, ((t->n[d] - 1) >> sh) + 1);
-        return m;
-    };
-    while (nb(bshift) > 64) ++bshift;
-    int mbits = 1;
-    while ((1 << mbits) < nb(bshift)) ++mbits;
-    L.bshift = bshift;
-    L.mbits = mbits;
-    L.nbins = 1 << (3 * mbits);
+    L.nbins = t->nbins;
     size_t off = 0;
-    L.off_counts = off;
-    off = align256(off + sizeof(int) * (size_t)(L.nbins + 1));
+    L.off_counts = off;   // nbins counts, then 8 per-XCD tile counters
+    off = align256(off + sizeof(int) * (size_t)(L.nbins + 8));
     L.off_cursor = off;
     off = align256(off + sizeof(int) * (size_t)L.nbins);
     L.off_keys = off;
@@ -182,9 +185,11 @@ static int enqueue_batched(const blip_table_s* t, const double* pos, const int64
     const SortLayout L = sort_layout(t, capacity);
     char* ws = static_cast<char*>(workspace);
     SortArgs sa;
-    sa.bshift = L.bshift;
-    sa.mbits = L.mbits;
-    sa.nbins = L.nbins;
+    sa.bshift = t->bshift;
+    sa.nb1 = t->nb[1];
+    sa.nb2 = t->nb[2];
+    sa.nbins = t->nbins;
+    sa.rank = t->d_brick_rank;
     sa.counts = reinterpret_cast<int*>(ws + L.off_counts);
     sa.cursor = reinterpret_cast<int*>(ws + L.off_cursor);
     sa.keys = reinterpret_cast<int*>(ws + L.off_keys);
@@ -195,10 +200,10 @@ static int enqueue_batched(const blip_table_s* t, const double* pos, const int64
     a.npos = capacity;
     a.dev_count = offsets + nw;
 
-    // counts are cleared by a kernel, not hipMemsetAsync, so the sequence
-    // can be captured into a graph and replayed
-    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_blocks(L.nbins + 1, 256, 1024)), dim3(256), 0, s,
-                       sa.counts, L.nbins + 1, 0);
+    // counts and the XCD tile counters are cleared by a kernel, not
+    // hipMemsetAsync, so the sequence can be captured into a graph and replayed
+    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_blocks(L.nbins + 8, 256, 1024)), dim3(256), 0, s,
+                       sa.counts, L.nbins + 8, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "fill kernel");
     const int g = grid_blocks(capacity, 256, 2048);
@@ -211,10 +216,12 @@ static int enqueue_batched(const blip_table_s* t, const double* pos, const int64
     hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, s, a, sa);
     e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "scatter kernel");
-    // persistent grid: about four workgroups per CU, never more than tiles
-    const int grid = grid_blocks(capacity, P, 4 * std::max(1, t->ncu));
+    // persistent grid: about four workgroups per CU, a multiple of 8 so that
+    // every XCD's tile range has workgroups, never many more than tiles
+    int grid = grid_blocks(capacity, P, 4 * std::max(1, t->ncu));
+    grid = std::max(8, (grid + 7) / 8 * 8);
     return launch_tiled(t, pos, capacity, val, grad, lap, KIND_TILED, P, OE, sa.perm,
-                        offsets + nw, grid, true, s);
+                        offsets + nw, sa.counts + L.nbins, grid, true, s);
 }
 
 static int batched_shape(const blip_table_s* t, int64_t capacity, int& P, int& OE)
@@ -354,7 +361,7 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
                 rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap, workspace,
                                                P, OE, s)
                              : launch_tiled(t, pos, npos, val, grad, lap, KIND_TILED, P, OE,
-                                            nullptr, nullptr, 0, false, s);
+                                            nullptr, nullptr, nullptr, 0, false, s);
                 (void)hipEventRecord(e1, s);
                 e = hipEventSynchronize(e1);
                 if (e != hipSuccess) rc = fail_hip(e, "autotune sync");

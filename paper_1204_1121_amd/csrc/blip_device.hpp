@@ -59,6 +59,7 @@ struct KArgs {
     int64_t npos;
     const int* perm;         // optional: slot -> original position index
     const int64_t* dev_count;// optional: device-side npos (persistent launch)
+    int* xcd_next;           // persistent launch: next-tile counter per XCD (8)
     void* val;               // [npos][W] float (double for FP64 accumulation)
     void* grad;              // [npos][3][W]
     void* lap;               // [npos][W]
@@ -228,6 +229,50 @@ __device__ __forceinline__ void load_elems(const char* p, ACC (&x)[OE])
     }
 }
 
+// Buffer-load form: o elements at byte offset voff (per lane, VGPR) + soff
+// (per row, SGPR) of a buffer resource.  Loads past the resource's record
+// count return zero instead of touching memory.
+constexpr int kBufWord3 = 0x00020000;   // gfx9-family raw-buffer word 3
+
+template <class E, int OE, class ACC>
+__device__ __forceinline__ void load_elems_buf(__amdgpu_buffer_rsrc_t r, int voff, int soff,
+                                               ACC (&x)[OE])
+{
+    constexpr int NW = (OE * E::bytes) / 4;
+    uint32_t w[NW];
+    if constexpr (NW == 1) {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    } else if constexpr (NW == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        w[0] = v[0];
+        w[1] = v[1];
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        w[0] = v[0];
+        w[1] = v[1];
+        w[2] = v[2];
+        w[3] = v[3];
+    }
+    if constexpr (E::bytes == 4) {
+#pragma unroll
+        for (int i = 0; i < OE; ++i) x[i] = (ACC)__uint_as_float(w[i]);
+    } else if constexpr (__is_same(E, BF16)) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            x[2 * i] = (ACC)__uint_as_float(w[i] << 16);
+            x[2 * i + 1] = (ACC)__uint_as_float(w[i] & 0xffff0000u);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(w[i] & 0xffffu));
+            const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(w[i] >> 16));
+            x[2 * i] = (ACC)(float)lo;
+            x[2 * i + 1] = (ACC)(float)hi;
+        }
+    }
+}
+
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -257,14 +302,17 @@ struct NOut { static constexpr int value = !FULL ? 1 : (ORTHO ? 5 : 10); };
 // The separable gather-accumulate for one (position, chunk) item.
 //   psi      = sum_m1 w1 sum_m2 w2 sum_m3 w3 a
 // and the derivative sums by replacing one or two factors with w' or w''.
-// cptr: this lane's first element within a row (chunk and lane offset
-// applied); rows are at cptr + row * row_bytes.
+// coef: table base; voff: this lane's byte offset within a row (chunk and
+// lane applied).  Each (i1, i2) line of n3 rows gets its own buffer
+// resource (64-bit base in SGPRs, record count n3 * row_bytes), and a row is
+// addressed by the SGPR offset i3 * row_bytes: no per-lane 64-bit address
+// arithmetic, and every load is bounds-checked by the hardware.
 // The outer m1 loop is kept rolled so that at most 16 row loads (one
 // 4x4 slab of the stencil) are in flight per wavefront; this bounds the
 // register footprint and lets several wavefronts share each SIMD.
 template <class E, int OE, bool FULL, bool ORTHO, class ACC>
-__device__ __forceinline__ void gather_item(const char* __restrict__ cptr,
-                                            int64_t row_bytes,
+__device__ __forceinline__ void gather_item(const char* __restrict__ coef, int voff,
+                                            int64_t row_bytes, int n3,
                                             const PosPrep<ACC>& pp,
                                             ACC (&out)[NOut<FULL, ORTHO>::value][OE])
 {
@@ -278,9 +326,10 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ cptr,
             w2[k][m] = uniform_f(pp.w[1][k][m]);
             w3[k][m] = uniform_f(pp.w[2][k][m]);
         }
-    uint64_t off3[4];
+    int off3[4];
 #pragma unroll
-    for (int m3 = 0; m3 < 4; ++m3) off3[m3] = (uint64_t)uniform_u(pp.i3[m3]) * (uint64_t)row_bytes;
+    for (int m3 = 0; m3 < 4; ++m3) off3[m3] = (int)(uniform_u(pp.i3[m3]) * (uint32_t)row_bytes);
+    const int line_bytes = (int)(n3 * row_bytes);
 
 #pragma unroll
     for (int q = 0; q < NO; ++q)
@@ -292,16 +341,16 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ cptr,
         ACC w1[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) w1[k] = uniform_f(pp.w[0][k][m1]);
-        uint64_t ob[4];
-#pragma unroll
-        for (int m2 = 0; m2 < 4; ++m2)
-            ob[m2] = (uint64_t)uniform_u(pp.rb[m1 * 4 + m2]) * (uint64_t)row_bytes;
         ACC x[4][4][OE];
 #pragma unroll
-        for (int m2 = 0; m2 < 4; ++m2)
+        for (int m2 = 0; m2 < 4; ++m2) {
+            const uint64_t ob = (uint64_t)uniform_u(pp.rb[m1 * 4 + m2]) * (uint64_t)row_bytes;
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char*>(coef) + ob, 0, line_bytes, kBufWord3);
 #pragma unroll
             for (int m3 = 0; m3 < 4; ++m3)
-                load_elems<E, OE, ACC>(cptr + ob[m2] + off3[m3], x[m2][m3]);
+                load_elems_buf<E, OE, ACC>(r, voff, off3[m3], x[m2][m3]);
+        }
 
         // middle-level sums over m2
         constexpr int NB = !FULL ? 1 : (ORTHO ? 4 : 6);
@@ -516,27 +565,31 @@ tiled_kernel(const KArgs a)
         if (npos < 0) npos = 0;
         ntiles = (int)((npos + P - 1) / P);
     }
-    const int nb = persist ? (int)gridDim.x : ntiles;
-    // persistent: workgroup b handles tiles of its XCD's contiguous share
-    const int first = persist ? 0 : xcd_tile(blockIdx.x, nb);
-    const int x = blockIdx.x % 8, kk = blockIdx.x / 8;
-    const int per_xcd_blocks = (nb - x + 7) / 8;
+    // Persistent launch: the tiles (in sorted order) are split into 8
+    // contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), and
+    // the workgroups of an XCD take the next tile of their range from a
+    // counter, so the tiles in flight on an XCD stay spatially close and
+    // share its L2.
+    const int x = blockIdx.x % 8;
     const int tq = ntiles / 8, tr = ntiles % 8;
     const int xcd_begin = x * tq + (x < tr ? x : tr);
     const int xcd_end = xcd_begin + tq + (x < tr ? 1 : 0);
+    __shared__ int s_next;
 
     for (int it = 0;; ++it) {
         int tile;
         if (persist) {
-            tile = xcd_begin + kk + it * per_xcd_blocks;
+            __syncthreads();   // previous tile's readers are done with prep[] and s_next
+            if (threadIdx.x == 0) s_next = atomicAdd(&a.xcd_next[x], 1);
+            __syncthreads();
+            tile = xcd_begin + s_next;
             if (tile >= xcd_end) break;
         } else {
             if (it > 0) break;
-            tile = first;
+            tile = xcd_tile(blockIdx.x, ntiles);
         }
         const int64_t j0 = (int64_t)tile * P;
         const int np = (int)((npos - j0) < P ? (npos - j0) : P);
-        __syncthreads();   // previous tile's readers are done with prep[]
         for (int p = threadIdx.x; p < np; p += blockDim.x) {
             const int64_t slot = j0 + p;
             const int64_t jo = a.perm ? (int64_t)a.perm[slot] : slot;
@@ -564,9 +617,9 @@ tiled_kernel(const KArgs a)
             // Lanes past the row end read element 0 of the chunk (in bounds,
             // discarded) so the loop below stays free of divergence.
             const int e_ld = lane_ok ? e0 : ch * kWave * OE;
-            const char* cptr = a.coef + (int64_t)e_ld * E::bytes;
             ACC acc[NO][OE];
-            gather_item<E, OE, FULL, ORTHO, ACC>(cptr, a.row_bytes, prep[p], acc);
+            gather_item<E, OE, FULL, ORTHO, ACC>(a.coef, e_ld * E::bytes, a.row_bytes, a.n3,
+                                                 prep[p], acc);
             ACC res[5][OE];
             finish_cartesian<FULL, ORTHO, ACC, OE>(a, acc, res);
             if constexpr (__is_same(E, F16)) {

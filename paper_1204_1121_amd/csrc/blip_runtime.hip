@@ -192,7 +192,7 @@ void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t
 
 int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
                  void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
-                 int grid, bool chunk_major, hipStream_t s)
+                 int* xcd_next, int grid, bool chunk_major, hipStream_t s)
 {
     KArgs a;
     fill_table_args(t, a);
@@ -203,6 +203,7 @@ int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* v
     a.lap = lap;
     a.perm = perm;
     a.dev_count = dev_count;
+    a.xcd_next = xcd_next;
     a.chunk_major = chunk_major ? 1 : 0;
     const int64_t ntiles = (npos + P - 1) / P;
     a.ntiles = (int)ntiles;
@@ -283,8 +284,8 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
         if (e != hipSuccess) return fail_hip(e, "kernel launch");
         return BLIP_OK;
     }
-    return launch_tiled(t, pos, npos, val, grad, lap, kind, P, OE, nullptr, nullptr, 0, false,
-                        static_cast<hipStream_t>(stream));
+    return launch_tiled(t, pos, npos, val, grad, lap, kind, P, OE, nullptr, nullptr, nullptr, 0,
+                        false, static_cast<hipStream_t>(stream));
 }
 
 }  // namespace blip
@@ -392,8 +393,10 @@ BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3, int norb
     }
     t->d_table = static_cast<char*>(d);
     int rc = upload_table(t, coeffs_host);
+    if (rc == BLIP_OK) rc = make_brick_ranks(t);
     if (rc != BLIP_OK) {
         (void)hipFree(d);
+        if (t->d_brick_rank) (void)hipFree(t->d_brick_rank);
         t->magic = 0;
         delete t;
         return rc;
@@ -434,6 +437,7 @@ BLIP_API int blip_free(blip_table t)
     if (cur != t->device) (void)hipSetDevice(t->device);
     hipError_t e = hipDeviceSynchronize();
     hipError_t e2 = hipFree(t->d_table);
+    if (t->d_brick_rank) (void)hipFree(t->d_brick_rank);
     if (cur != t->device && cur >= 0) (void)hipSetDevice(cur);
     t->magic = 0;
     delete t;

@@ -49,6 +49,12 @@ struct blip_table_s {
     size_t table_bytes;
     char* d_table;
     float out_scale;     // 2^-e for FP16 tables stored as a * 2^e
+    // spatial bins for batch sorting: bricks of 2^bshift cells per side,
+    // numbered by their rank along a Morton (Z-order) curve
+    int bshift;
+    int nb[3];
+    int nbins;
+    int* d_brick_rank;   // [nb0][nb1][nb2] -> Morton rank
     mutable std::mutex tune_mu;
     std::vector<blip::TuneEntry> tune[2];   // indexed by blip::TuneMode
 };
@@ -67,12 +73,13 @@ void set_tuned(blip_table_s* t, int mode, int64_t npos, int P, int OE);
 // sorted persistent form used for batches; grid is then the workgroup count.
 int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
                  void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
-                 int grid, bool chunk_major, hipStream_t s);
+                 int* xcd_next, int grid, bool chunk_major, hipStream_t s);
 bool valid_oe(const blip_table_s* t, int OE);
 int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
                     void* lap);
 void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t grid, Cfg& c,
               KArgs& a);
 int upload_table(blip_table_s* t, const void* host);
+int make_brick_ranks(blip_table_s* t);
 
 }  // namespace blip

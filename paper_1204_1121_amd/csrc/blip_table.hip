@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "blip_runtime.hpp"
 
@@ -22,6 +24,56 @@ static int fp16_exponent(const float* a, int64_t count)
     if (mx == 0.0f) return 0;
     int e = 14 - (int)std::ceil(std::log2((double)mx));
     return std::max(-24, std::min(24, e));
+}
+
+// Bricks of 2^bshift cells per side (bshift >= 2, grown until there are at
+// most 16384 bricks), ranked along a Morton curve so consecutive bins of
+// the batch sort are spatial neighbours.
+int make_brick_ranks(blip_table_s* t)
+{
+    int bshift = 2;
+    auto count = [&](int sh, int* nb) {
+        int64_t tot = 1;
+        for (int d = 0; d < 3; ++d) {
+            nb[d] = ((t->n[d] - 1) >> sh) + 1;
+            tot *= nb[d];
+        }
+        return tot;
+    };
+    int nb[3];
+    while (count(bshift, nb) > 16384) ++bshift;
+    const int nbins = nb[0] * nb[1] * nb[2];
+    auto spread = [](uint32_t v) {
+        uint64_t r = 0;
+        for (int b = 0; b < 21; ++b) r |= (uint64_t)((v >> b) & 1u) << (3 * b);
+        return r;
+    };
+    std::vector<std::pair<uint64_t, int>> order((size_t)nbins);
+    for (int i = 0; i < nb[0]; ++i)
+        for (int j = 0; j < nb[1]; ++j)
+            for (int k = 0; k < nb[2]; ++k) {
+                const int idx = (i * nb[1] + j) * nb[2] + k;
+                order[(size_t)idx] = {(spread(i) << 2) | (spread(j) << 1) | spread(k), idx};
+            }
+    std::sort(order.begin(), order.end());
+    std::vector<int> rank((size_t)nbins);
+    for (int r = 0; r < nbins; ++r) rank[(size_t)order[(size_t)r].second] = r;
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int) * (size_t)nbins);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BLIP_E_OOM, "hipMalloc of the brick rank table failed");
+    }
+    e = hipMemcpy(d, rank.data(), sizeof(int) * (size_t)nbins, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail_hip(e, "hipMemcpy(brick ranks)");
+    }
+    t->bshift = bshift;
+    for (int dd = 0; dd < 3; ++dd) t->nb[dd] = nb[dd];
+    t->nbins = nbins;
+    t->d_brick_rank = static_cast<int*>(d);
+    return BLIP_OK;
 }
 
 int upload_table(blip_table_s* t, const void* host)
