@@ -34,24 +34,18 @@ _KIND = {np.dtype(np.float64): 0, np.dtype(np.float32): 1,
 _lib = None
 
 
-def build() -> str:
+def build(src: str = _SRC, out: str = _LIB_PATH) -> str:
     """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
-    tmp = _LIB_PATH + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-o", tmp, _SRC, "-lm"]
+           "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+def _bind(lib):
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     for name in ("oracle_phi", "oracle_dphi", "oracle_d2phi"):
@@ -67,86 +61,139 @@ def _load():
                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                 dp, dp, ctypes.c_int64, dp, dp, dp,
                                 ctypes.c_int]
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
 
 
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+class Oracle:
+    """The C oracle bound to one compiled library (the default build, or a
+    variant compiled from a modified source by the mutation tests)."""
+
+    def __init__(self, lib):
+        self._lib = lib
+
+    def phi(self, x, deriv: int = 0) -> np.ndarray:
+        """The 1-D cubic B-spline phi (deriv 0), phi' (1) or phi'' (2)."""
+        lib = self._lib
+        fn = (lib.oracle_phi, lib.oracle_dphi, lib.oracle_d2phi)[deriv]
+        xs = np.asarray(x, dtype=np.float64)
+        return np.vectorize(lambda v: fn(float(v)), otypes=[np.float64])(xs)
+
+
+    def inverse3(self, lattice) -> np.ndarray:
+        """A^{-1} by cofactors, as the oracle forms it (raises if singular)."""
+        lib = self._lib
+        A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        G = np.zeros(9)
+        if lib.oracle_inverse3(_dptr(A), _dptr(G)) != 0:
+            raise ValueError("singular lattice")
+        return G.reshape(3, 3)
+
+
+    def wrap(self, lattice, n, r):
+        """Cell index i0 and offset f of position r (the subset selection, Eq. (7))."""
+        lib = self._lib
+        G = np.ascontiguousarray(self.inverse3(lattice).reshape(9))
+        nn = (ctypes.c_int * 3)(*[int(v) for v in n])
+        rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
+        i0 = (ctypes.c_int * 3)()
+        f = np.zeros(3)
+        rc = lib.oracle_wrap(_dptr(G), nn, _dptr(rr), i0, _dptr(f))
+        return np.array(list(i0), dtype=np.int64), f, rc == 0
+
+
+    def evaluate(self, lattice, n, coef, pos, kvec=None, want=("val", "grad", "lap"),
+                 nthreads: int = 1):
+        """Orbitals (and gradients, Laplacians) at every position, in FP64.
+
+        lattice: 3x3 rows a_1..a_3 (bohr); n: (n1, n2, n3);
+        coef: array [n1, n2, n3, L] of float64/float32/complex128/complex64;
+        pos: [npos, 3] Cartesian bohr; kvec: k-point (complex tables only).
+        Returns a dict with ``val`` [npos, L], ``grad`` [npos, 3, L] and
+        ``lap`` [npos, L] for the requested keys.
+        """
+        lib = self._lib
+        coef = np.ascontiguousarray(coef)
+        if coef.dtype not in _KIND:
+            raise TypeError(f"unsupported coefficient dtype {coef.dtype}")
+        n1, n2, n3 = (int(v) for v in n)
+        if coef.ndim != 4 or coef.shape[:3] != (n1, n2, n3):
+            raise ValueError("coef must be [n1, n2, n3, L]")
+        L = int(coef.shape[3])
+        cplx = np.iscomplexobj(coef)
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        npos = pos.shape[0]
+        A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        odt = np.complex128 if cplx else np.float64
+        out = {}
+        if "val" in want:
+            out["val"] = np.zeros((npos, L), dtype=odt)
+        if "grad" in want:
+            out["grad"] = np.zeros((npos, 3, L), dtype=odt)
+        if "lap" in want:
+            out["lap"] = np.zeros((npos, L), dtype=odt)
+        k = None
+        if kvec is not None:
+            k = np.ascontiguousarray(np.asarray(kvec, dtype=np.float64).reshape(3))
+        null = ctypes.POINTER(ctypes.c_double)()
+        rc = lib.oracle_eval(
+            _dptr(A), n1, n2, n3, L, coef.ctypes.data_as(ctypes.c_void_p),
+            _KIND[coef.dtype], _dptr(k) if k is not None else null,
+            _dptr(pos), npos,
+            _dptr(out["val"]) if "val" in out else null,
+            _dptr(out["grad"]) if "grad" in out else null,
+            _dptr(out["lap"]) if "lap" in out else null,
+            int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle_eval rejected its arguments")
+        return out
+
+
+_default = None
+
+
+def _oracle() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(_load())
+    return _default
+
+
+def load_variant(path: str) -> Oracle:
+    """An Oracle bound to another compiled build of blip_oracle.c."""
+    return Oracle(_bind(ctypes.CDLL(path)))
+
+
 def phi(x, deriv: int = 0) -> np.ndarray:
     """The 1-D cubic B-spline phi (deriv 0), phi' (1) or phi'' (2)."""
-    lib = _load()
-    fn = (lib.oracle_phi, lib.oracle_dphi, lib.oracle_d2phi)[deriv]
-    xs = np.asarray(x, dtype=np.float64)
-    return np.vectorize(lambda v: fn(float(v)), otypes=[np.float64])(xs)
+    return _oracle().phi(x, deriv)
 
 
 def inverse3(lattice) -> np.ndarray:
     """A^{-1} by cofactors, as the oracle forms it (raises if singular)."""
-    lib = _load()
-    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
-    G = np.zeros(9)
-    if lib.oracle_inverse3(_dptr(A), _dptr(G)) != 0:
-        raise ValueError("singular lattice")
-    return G.reshape(3, 3)
+    return _oracle().inverse3(lattice)
 
 
 def wrap(lattice, n, r):
     """Cell index i0 and offset f of position r (the subset selection, Eq. (7))."""
-    lib = _load()
-    G = np.ascontiguousarray(inverse3(lattice).reshape(9))
-    nn = (ctypes.c_int * 3)(*[int(v) for v in n])
-    rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(3))
-    i0 = (ctypes.c_int * 3)()
-    f = np.zeros(3)
-    rc = lib.oracle_wrap(_dptr(G), nn, _dptr(rr), i0, _dptr(f))
-    return np.array(list(i0), dtype=np.int64), f, rc == 0
+    return _oracle().wrap(lattice, n, r)
 
 
 def evaluate(lattice, n, coef, pos, kvec=None, want=("val", "grad", "lap"),
              nthreads: int = 1):
-    """Orbitals (and gradients, Laplacians) at every position, in FP64.
-
-    lattice: 3x3 rows a_1..a_3 (bohr); n: (n1, n2, n3);
-    coef: array [n1, n2, n3, L] of float64/float32/complex128/complex64;
-    pos: [npos, 3] Cartesian bohr; kvec: k-point (complex tables only).
-    Returns a dict with ``val`` [npos, L], ``grad`` [npos, 3, L] and
-    ``lap`` [npos, L] for the requested keys.
-    """
-    lib = _load()
-    coef = np.ascontiguousarray(coef)
-    if coef.dtype not in _KIND:
-        raise TypeError(f"unsupported coefficient dtype {coef.dtype}")
-    n1, n2, n3 = (int(v) for v in n)
-    if coef.ndim != 4 or coef.shape[:3] != (n1, n2, n3):
-        raise ValueError("coef must be [n1, n2, n3, L]")
-    L = int(coef.shape[3])
-    cplx = np.iscomplexobj(coef)
-    pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
-    npos = pos.shape[0]
-    A = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
-    odt = np.complex128 if cplx else np.float64
-    out = {}
-    if "val" in want:
-        out["val"] = np.zeros((npos, L), dtype=odt)
-    if "grad" in want:
-        out["grad"] = np.zeros((npos, 3, L), dtype=odt)
-    if "lap" in want:
-        out["lap"] = np.zeros((npos, L), dtype=odt)
-    k = None
-    if kvec is not None:
-        k = np.ascontiguousarray(np.asarray(kvec, dtype=np.float64).reshape(3))
-    null = ctypes.POINTER(ctypes.c_double)()
-    rc = lib.oracle_eval(
-        _dptr(A), n1, n2, n3, L, coef.ctypes.data_as(ctypes.c_void_p),
-        _KIND[coef.dtype], _dptr(k) if k is not None else null,
-        _dptr(pos), npos,
-        _dptr(out["val"]) if "val" in out else null,
-        _dptr(out["grad"]) if "grad" in out else null,
-        _dptr(out["lap"]) if "lap" in out else null,
-        int(nthreads))
-    if rc != 0:
-        raise ValueError("oracle_eval rejected its arguments")
-    return out
+    """Orbitals (and gradients, Laplacians) at every position, in FP64;
+    see Oracle.evaluate."""
+    return _oracle().evaluate(lattice, n, coef, pos, kvec=kvec, want=want, nthreads=nthreads)

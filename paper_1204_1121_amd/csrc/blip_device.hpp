@@ -336,12 +336,9 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
 #pragma unroll
         for (int e = 0; e < OE; ++e) out[q][e] = (ACC)0;
 
-#pragma unroll 1
-    for (int m1 = 0; m1 < 4; ++m1) {
-        ACC w1[ND];
-#pragma unroll
-        for (int k = 0; k < ND; ++k) w1[k] = uniform_f(pp.w[0][k][m1]);
-        ACC x[4][4][OE];
+    // Slab m1 (4x4 rows) is loaded one iteration ahead: while slab m1 is
+    // summed, the 16 loads of slab m1+1 are already in flight.
+    auto load_slab = [&](int m1, ACC (&x)[4][4][OE]) {
 #pragma unroll
         for (int m2 = 0; m2 < 4; ++m2) {
             const uint64_t ob = (uint64_t)uniform_u(pp.rb[m1 * 4 + m2]) * (uint64_t)row_bytes;
@@ -351,6 +348,23 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
             for (int m3 = 0; m3 < 4; ++m3)
                 load_elems_buf<E, OE, ACC>(r, voff, off3[m3], x[m2][m3]);
         }
+    };
+    ACC xn[4][4][OE];
+    load_slab(0, xn);
+
+#pragma unroll 1
+    for (int m1 = 0; m1 < 4; ++m1) {
+        ACC w1[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) w1[k] = uniform_f(pp.w[0][k][m1]);
+        ACC x[4][4][OE];
+#pragma unroll
+        for (int m2 = 0; m2 < 4; ++m2)
+#pragma unroll
+            for (int m3 = 0; m3 < 4; ++m3)
+#pragma unroll
+                for (int e = 0; e < OE; ++e) x[m2][m3][e] = xn[m2][m3][e];
+        if (m1 < 3) load_slab(m1 + 1, xn);
 
         // middle-level sums over m2
         constexpr int NB = !FULL ? 1 : (ORTHO ? 4 : 6);
@@ -495,6 +509,9 @@ __device__ __forceinline__ void apply_bloch(const KArgs& a, float cph, float sph
     }
 }
 
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
 // Store o consecutive outputs at p (vector stores when allowed, else masked
 // element stores against the row length W).  Outputs are float, or double
 // for the FP64-accumulate debug kernel.
@@ -502,20 +519,26 @@ template <int OE>
 __device__ __forceinline__ void store_elems(float* p, const float (&v)[OE], int e0,
                                             int W, bool vec)
 {
+    // Outputs are written once and read by the consumer later: non-temporal
+    // stores keep them from displacing table rows in L2 and the Infinity Cache.
     if (vec && e0 + OE <= W) {
         if constexpr (OE == 1) {
-            *p = v[0];
+            __builtin_nontemporal_store(v[0], p);
         } else if constexpr (OE == 2) {
-            *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+            const vf2 x = {v[0], v[1]};
+            __builtin_nontemporal_store(x, reinterpret_cast<vf2*>(p));
         } else {
 #pragma unroll
             for (int i = 0; i < OE; i += 4)
-                *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+            {
+                const vf4 x = {v[i], v[i + 1], v[i + 2], v[i + 3]};
+                __builtin_nontemporal_store(x, reinterpret_cast<vf4*>(p + i));
+            }
         }
     } else {
 #pragma unroll
         for (int i = 0; i < OE; ++i)
-            if (e0 + i < W) p[i] = v[i];
+            if (e0 + i < W) __builtin_nontemporal_store(v[i], p + i);
     }
 }
 
