@@ -69,10 +69,31 @@ def distinct_rows(lattice, n, pos) -> int:
     return int(np.unique(rows.reshape(-1)).size)
 
 
+def time_region(fn, blocks, steps, warmup, stream):
+    """The timed region: warmup untimed steps, then exactly `steps` steps
+    bracketed by synchronisation, with one HIP event pair on the launch
+    stream around them.  Returns (wall seconds, mean GPU seconds per step
+    from the events)."""
+    import torch
+    for i in range(warmup):
+        fn(blocks[i % len(blocks)])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        fn(blocks[(warmup + i) % len(blocks)])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) * 1e-3 / steps
+
+
 def time_launches(fn, blocks, steps, warmup, stream, pre=None):
     """Run fn(block) warmup+steps times; returns (wall seconds for the timed
-    steps, per-launch durations in seconds from events on `stream`).
-    ``pre`` (optional) runs before each launch, outside its event pair."""
+    steps, per-launch durations in seconds from an event pair around each
+    launch).  ``pre`` (optional) runs before each launch, outside its pair."""
     import torch
     for i in range(warmup):
         fn(blocks[i % len(blocks)])
@@ -121,6 +142,7 @@ def bench_batched(table, spec, args, nbatch=4):
     the plain kernel on the concatenation and per-walker launch loops."""
     import torch
     from paper_1204_1121_amd import workloads as wl
+    from paper_1204_1121_amd.tuning import TuneCache
     stream = torch.cuda.current_stream()
     bs = [wl.walker_batch(spec, nwalkers=512, max_block=256, batch=q) for q in range(nbatch)]
     cap = max(b.pos.shape[0] for b in bs)
@@ -129,16 +151,27 @@ def bench_batched(table, spec, args, nbatch=4):
     off = [torch.from_numpy(b.offsets).cuda() for b in bs]
     out = table.alloc_outputs(cap)
     ws = table.workspace(cap)
-    best, allr = table.autotune(pos[0], out, offsets=off[0], workspace=ws, capacity=cap)
-    log(f"batched autotune: P={best['tile_pos']} o={best['vec']} ({best['us']:.0f} us)")
+    cache = TuneCache()
+    allr = None
+    if not args.retune and cache.apply(table, cap, batched=True):
+        best = dict(cache.get(table, cap, True), **{"from": "tuning cache"})
+    else:
+        best, allr = table.autotune(pos[0], out, offsets=off[0], workspace=ws, capacity=cap)
+        cache.put(table, cap, True, best, note="blip_autotune, 512-walker batch")
+        best["from"] = "autotuned now"
+        if args.save_tuning:
+            cache.entries.update(TuneCache(args.save_tuning).entries
+                                 if os.path.exists(args.save_tuning) else {})
+            cache.put(table, cap, True, best, note="blip_autotune, 512-walker batch")
+            cache.save(args.save_tuning)
+    log(f"batched shape: P={best['tile_pos']} o={best['vec']} ({best['from']})")
     plans = [table.plan(p, o, out, ws, capacity=p.shape[0]) for p, o in zip(pos, off)]
     steps = max(10, min(args.steps, 50))
-    wall, durs = time_launches(lambda i: plans[i].launch(), list(range(nbatch)), steps, 3, stream)
+    wall, t_b = time_region(lambda i: plans[i].launch(), list(range(nbatch)), steps, 3, stream)
     npos_mean = float(np.mean([b.pos.shape[0] for b in bs]))
-    t_b = float(np.mean(durs))
     U = [distinct_rows(spec.lattice, spec.n, b.pos) for b in bs]
     b_alg = float(np.mean([u * L * 4 + b.pos.shape[0] * (5 * L * 4 + 24) for u, b in zip(U, bs)]))
-    res = {"walkers": 512, "positions_mean": npos_mean, "tuned": best, "autotune": allr,
+    res = {"walkers": 512, "positions_mean": npos_mean, "shape": best, "autotune": allr,
            "value": npos_mean * L * steps / wall, "unit": UNIT,
            "launch_us": t_b * 1e6, "hbm_gbs": b_alg / t_b / 1e9,
            "frac": b_alg / t_b / 1e9 / HBM_PEAK_GBS, "bytes_algorithmic": b_alg,
@@ -268,6 +301,11 @@ def main():
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache measurement (profiling runs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-walker batch")
+    ap.add_argument("--shape", default="", help="fixed block launch shape 'P,o' (no tuning)")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner even if the tuning cache has the shapes")
+    ap.add_argument("--save-tuning", default="",
+                    help="write the shapes chosen by this run to this JSON file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving rate point")
@@ -283,6 +321,7 @@ def main():
     import torch
     from paper_1204_1121_amd import blip
     from paper_1204_1121_amd import workloads as wl
+    from paper_1204_1121_amd.tuning import TuneCache
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -303,21 +342,34 @@ def main():
     blocks = [torch.from_numpy(b).cuda() for b in blocks_np]
     out = table.alloc_outputs(npos)
 
-    # pick the launch shape for this block size with the library's autotuner
-    # (setup, outside the timed region)
-    best, _ = table.autotune(blocks[0], out)
-    log(f"autotuned block shape: P={best['tile_pos']} o={best['vec']} ({best['us']:.1f} us)")
+    # launch shape: the cached autotuning result for this table and size, or
+    # a fresh run of the library's autotuner rotating over the benchmark's
+    # blocks (setup, outside the timed region)
+    cache = TuneCache()
+    if args.shape:
+        P_, o_ = (int(v) for v in args.shape.split(","))
+        table.set_shape(npos, P_, o_)
+        best = {"tile_pos": P_, "vec": o_, "us": float("nan"), "from": "--shape"}
+    elif not args.retune and cache.apply(table, npos):
+        best = dict(cache.get(table, npos), **{"from": "tuning cache"})
+    else:
+        best, _ = table.autotune(torch.cat(blocks).contiguous(), out, rotate=NROT)
+        cache.put(table, npos, False, best, note=f"blip_autotune rotate={NROT}")
+        best["from"] = "autotuned now"
+    log(f"block shape: P={best['tile_pos']} o={best['vec']} ({best['from']})")
     calls = {id(b): table.bind(b, out) for b in blocks}
 
     def step(pos):
         calls[id(pos)]()
 
-    wall, durs = time_launches(step, blocks, args.steps, args.warmup, stream)
+    wall, t_kernel = time_region(step, blocks, args.steps, args.warmup, stream)
     ms_per_step = wall / args.steps * 1e3
     value = npos * L * args.steps / wall
-    t_kernel = float(np.mean(durs))
-    log(f"tuned: {ms_per_step * 1e3:.1f} us/step wall, kernel {t_kernel * 1e6:.1f} us "
-        f"(median {np.median(durs) * 1e6:.1f})")
+    # per-launch spread, from a separate pass with an event pair per launch
+    _, durs = time_launches(step, blocks, args.steps, 4, stream)
+    log(f"tuned: {ms_per_step * 1e3:.1f} us/step wall, {t_kernel * 1e6:.1f} us/launch on the "
+        f"GPU (per-launch events: median {np.median(durs) * 1e6:.1f}, "
+        f"p99 {np.percentile(durs, 99) * 1e6:.1f})")
 
     # algorithmic bytes per launch: distinct rows + outputs + positions
     row_bytes = L * 4
@@ -348,8 +400,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "kernel_us": {"mean": t_kernel * 1e6, "median": float(np.median(durs)) * 1e6,
-                      "p99": float(np.percentile(durs, 99)) * 1e6},
+        "kernel_us": {"mean": t_kernel * 1e6,
+                      "per_launch_events_median": float(np.median(durs)) * 1e6,
+                      "per_launch_events_p99": float(np.percentile(durs, 99)) * 1e6},
+        "shape": {"tile_pos": best["tile_pos"], "vec": best["vec"], "from": best["from"]},
         "bytes_per_launch": {"algorithmic": b_alg_mean, "gather_no_reuse": b_gather,
                              "distinct_rows": float(np.mean(U))},
     }
@@ -357,8 +411,7 @@ def main():
     if not args.no_plain:
         def plain_step(pos):
             table.eval(pos, out=out, kernel="plain")
-        wall_p, durs_p = time_launches(plain_step, blocks, args.steps, args.warmup, stream)
-        tp = float(np.mean(durs_p))
+        wall_p, tp = time_region(plain_step, blocks, args.steps, args.warmup, stream)
         result["plain"] = {"value": npos * L * args.steps / wall_p,
                            "kernel_us": tp * 1e6,
                            "hbm_gbs": b_alg_mean / tp / 1e9,
@@ -380,6 +433,9 @@ def main():
                                 "frac": b_alg_mean / tc / 1e9 / HBM_PEAK_GBS}
         log(f"cold-cache: kernel {tc * 1e6:.1f} us")
         del sweep
+
+    if args.save_tuning:
+        cache.save(args.save_tuning)
 
     if not args.no_batched:
         try:

@@ -107,7 +107,8 @@ typedef struct {
  *              psi = exp(i k.r) u with u the spline sum; NULL = Gamma.
  *              A kvec with a real storage dtype is BLIP_E_DTYPE.
  *  out         receives the handle (NULL on failure).
- * Device memory: n1*n2*n3 rows of roundup(L * element bytes, 128) bytes.
+ * Device memory: n1*n2*n3 rows of roundup(L * element bytes, 128) bytes;
+ * n3 times that row size must stay below 2 GiB (BLIP_E_ARG otherwise).
  * Synchronous: returns after the table is resident.  Errors: BLIP_E_ARG,
  * BLIP_E_DTYPE, BLIP_E_OOM, BLIP_E_HIP, BLIP_E_NODEV.
  */
@@ -197,8 +198,11 @@ BLIP_API int blip_plan_free(blip_plan p);
  * blip_autotune -- time every launch shape (P positions per workgroup x o
  * table elements per lane) on the caller's buffers and keep the fastest for
  * this table and this size bucket (npos in [2^k, 2^(k+1))).  offsets == NULL
- * tunes blip_eval on pos[npos] (P in {1,2,4,8}); otherwise it tunes
- * blip_eval_batched with capacity npos (P in {8,16,32,64}).  o runs over
+ * tunes blip_eval on blocks of npos positions (P in {1,2,4,8}): pos then
+ * holds `rotate` consecutive blocks and timed launch i uses block i mod
+ * rotate, so that a launch does not find its rows left in the caches by the
+ * previous one; otherwise (rotate must be 1) it tunes blip_eval_batched with
+ * capacity npos (P in {8,16,32,64}).  o runs over
  * {1,2,4} (FP32 storage) or {2,4,8} (16-bit storage).  Synchronous: it
  * synchronises the stream after each timed launch.  The outputs are
  * overwritten.  results (may be NULL) receives up to max_results timings;
@@ -210,9 +214,10 @@ typedef struct {
     double us;      /* median launch time, microseconds */
 } blip_tune_result;
 BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offsets, int nw,
-                           int64_t npos, void* val, void* grad, void* lap, void* workspace,
-                           size_t workspace_bytes, void* stream, blip_tune_result* results,
-                           int max_results, int* n_results, blip_tune_result* best);
+                           int64_t npos, int rotate, void* val, void* grad, void* lap,
+                           void* workspace, size_t workspace_bytes, void* stream,
+                           blip_tune_result* results, int max_results, int* n_results,
+                           blip_tune_result* best);
 
 /* blip_set_shape / blip_get_shape -- set or read the launch shape used for
  * npos's size bucket (batched != 0: the batched path), e.g. to restore a

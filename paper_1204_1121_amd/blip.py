@@ -74,7 +74,7 @@ def lib() -> ctypes.CDLL:
     L.blip_plan_free.restype = ci
     L.blip_plan_free.argtypes = [vp]
     L.blip_autotune.restype = ci
-    L.blip_autotune.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp, ctypes.c_size_t, vp,
+    L.blip_autotune.argtypes = [vp, vp, vp, ci, i64, ci, vp, vp, vp, vp, ctypes.c_size_t, vp,
                                 ctypes.POINTER(TuneResult), ci, ctypes.POINTER(ci),
                                 ctypes.POINTER(TuneResult)]
     L.blip_set_shape.restype = ci
@@ -232,23 +232,28 @@ class Table:
         return Plan(self, pos, offsets, out, workspace, capacity)
 
     def autotune(self, pos, out, offsets=None, workspace=None, capacity: int | None = None,
-                 stream=None):
+                 rotate: int = 1, stream=None):
         """Time every (P, o) and keep the fastest for this size bucket.
+        Blocks: pos holds ``rotate`` blocks of out's row count, used in turn.
         Returns (best, all) as dicts {tile_pos, vec, us}."""
         val, g, lap = out
         res = (TuneResult * 32)()
         n = ctypes.c_int()
         best = TuneResult()
         if offsets is None:
-            check(lib().blip_autotune(self.handle, _ptr(pos), None, 0, pos.shape[0], _ptr(val),
-                                      _ptr(g), _ptr(lap), None, 0, _stream_ptr(stream), res, 32,
-                                      ctypes.byref(n), ctypes.byref(best)))
+            npos = val.shape[0]
+            if pos.shape[0] != npos * rotate:
+                raise ValueError("pos must hold rotate blocks of the outputs' row count")
+            check(lib().blip_autotune(self.handle, _ptr(pos), None, 0, npos, int(rotate),
+                                      _ptr(val), _ptr(g), _ptr(lap), None, 0,
+                                      _stream_ptr(stream), res, 32, ctypes.byref(n),
+                                      ctypes.byref(best)))
         else:
             cap = pos.shape[0] if capacity is None else int(capacity)
             if workspace is None:
                 workspace = self.workspace(cap, pos.device)
             check(lib().blip_autotune(self.handle, _ptr(pos), _ptr(offsets),
-                                      int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
+                                      int(offsets.shape[0]) - 1, cap, 1, _ptr(val), _ptr(g),
                                       _ptr(lap), _ptr(workspace), workspace.numel(),
                                       _stream_ptr(stream), res, 32, ctypes.byref(n),
                                       ctypes.byref(best)))

@@ -329,11 +329,14 @@ BLIP_API int blip_plan_free(blip_plan p)
 }
 
 BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offsets, int nw,
-                           int64_t npos, void* val, void* grad, void* lap, void* workspace,
-                           size_t workspace_bytes, void* stream, blip_tune_result* results,
-                           int max_results, int* n_results, blip_tune_result* best)
+                           int64_t npos, int rotate, void* val, void* grad, void* lap,
+                           void* workspace, size_t workspace_bytes, void* stream,
+                           blip_tune_result* results, int max_results, int* n_results,
+                           blip_tune_result* best)
 {
     const bool batched = offsets != nullptr;
+    if (rotate < 1) return fail(BLIP_E_ARG, "rotate must be >= 1 (got %d)", rotate);
+    if (batched && rotate != 1) return fail(BLIP_E_ARG, "rotate applies to blocks (offsets == NULL)");
     int rc = batched ? check_batched_args(t, pos, offsets, nw, npos, val, grad, lap, workspace,
                                           workspace_bytes)
                      : check_eval_args(t, pos, npos, val, grad, lap);
@@ -356,11 +359,15 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
         for (int OE : Os) {
             if (!valid_oe(t, OE)) continue;
             std::vector<float> ts;
-            for (int it = 0; it < 9 && rc == BLIP_OK; ++it) {
+            const int iters = 2 + std::max(7, rotate);
+            for (int it = 0; it < iters && rc == BLIP_OK; ++it) {
                 (void)hipEventRecord(e0, s);
+                // blocks rotate so a launch does not find its rows left in
+                // the caches by the launch before (as in a running simulation)
+                const double* pb = pos + 3 * npos * (int64_t)(it % rotate);
                 rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap, workspace,
                                                P, OE, s)
-                             : launch_tiled(t, pos, npos, val, grad, lap, KIND_TILED, P, OE,
+                             : launch_tiled(t, pb, npos, val, grad, lap, KIND_TILED, P, OE,
                                             nullptr, nullptr, nullptr, 0, false, s);
                 (void)hipEventRecord(e1, s);
                 e = hipEventSynchronize(e1);

@@ -327,6 +327,17 @@ BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3, int norb
     const int64_t W64 = (int64_t)norb * (cplx ? 2 : 1);
     if (W64 > (int64_t)1 << 24) return fail(BLIP_E_ARG, "norb too large (%d)", norb);
 
+    {
+        // the kernels address one (i1, i2) line of n3 rows through a buffer
+        // resource with a 32-bit record count and 32-bit offsets
+        const bool half16 = storage == BLIP_BF16 || storage == BLIP_F16 ||
+                            storage == BLIP_CBF16 || storage == BLIP_CF16;
+        const int64_t rowb = (W64 * (half16 ? 2 : 4) + 127) / 128 * 128;
+        if ((int64_t)n3 * rowb >= ((int64_t)1 << 31))
+            return fail(BLIP_E_ARG, "n3 x row bytes (%lld) must stay below 2 GiB",
+                        (long long)((int64_t)n3 * rowb));
+    }
+
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(BLIP_E_NODEV, "no HIP device: %s", hipGetErrorString(e));

@@ -76,6 +76,14 @@ def test_load_argument_errors(blip):
     assert _load(blip, storage=0, kvec=[0.1, 0, 0])[0] == -4   # k-point on real table
     msg = blip.lib().blip_last_error().decode()
     assert "complex" in msg
+    # one (i1, i2) line of n3 rows must stay below 2 GiB: n3 = 4096 rows of
+    # 2^20 floats (4 MiB each) is 16 GiB; rejected before any allocation
+    L = blip.lib()
+    A = np.ascontiguousarray(np.eye(3) * 4.0)
+    h = ctypes.c_void_p()
+    rc = L.blip_load(A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4, 4, 4096, 1 << 20,
+                     ctypes.c_void_p(1), 0, None, ctypes.byref(h))
+    assert rc == -1 and "2 GiB" in L.blip_last_error().decode()
 
 
 def test_eval_rejects_bad_handle(blip):

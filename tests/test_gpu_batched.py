@@ -147,6 +147,11 @@ def test_autotune(blip, small):
     out = t.alloc_outputs(pos.shape[0])
     say("autotune block and batched")
     best, allr = t.autotune(p, out)
+    with pytest.raises(ValueError):
+        t.autotune(p, out, rotate=2)          # pos must hold 2 blocks
+    half = pos.shape[0] // 2
+    b2, _ = t.autotune(p[: 2 * half].contiguous(), t.alloc_outputs(half), rotate=2)
+    assert b2["us"] > 0
     assert len(allr) == 12 and best in allr
     assert t.get_shape(pos.shape[0]) == (best["tile_pos"], best["vec"])
     best_b, allb = t.autotune(p, out, offsets=o)
