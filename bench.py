@@ -276,6 +276,50 @@ def bench_serving(args):
     return out
 
 
+def bench_precision(args, real_coef, real_spec, cache):
+    """Storage dtypes at 1,536 positions: the complex k-point table (384
+    orbitals) as complex64 / BF16 pairs / FP16 pairs, and the 768-orbital real
+    table as FP32 / BF16 / FP16.  For each: kernel time, evals/s and the
+    normwise max relative error of val, grad and lap against the FP64 oracle
+    on the FP32 master, over the whole block."""
+    import torch
+    import oracle
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    threads = len(os.sched_getaffinity(0))
+    out = {}
+    cases = [("complex_k", wl.spec_tio2_complex(), None, ("c64", "cbf16", "cf16")),
+             ("real", real_spec, real_coef, ("f32", "bf16", "f16"))]
+    for label, spec, coef, dtypes in cases:
+        if coef is None:
+            coef = wl.coefficients(spec)
+        blocks = [torch.from_numpy(wl.move_block(spec, 1536, block=b)).cuda() for b in range(NROT)]
+        pos0 = wl.move_block(spec, 1536, block=0)
+        ref = oracle.evaluate(spec.lattice, spec.n, coef, pos0, kvec=spec.kvec, nthreads=threads)
+        for st in dtypes:
+            t = blip.Table(spec.lattice, spec.n, coef, st, kvec=spec.kvec)
+            o = t.alloc_outputs(1536)
+            if args.retune or not cache.apply(t, 1536):
+                best, _ = t.autotune(torch.cat(blocks).contiguous(), o, rotate=NROT)
+                cache.put(t, 1536, False, best, note=f"blip_autotune rotate={NROT}")
+            calls = {id(b): t.bind(b, o) for b in blocks}
+            wall, tk = time_region(lambda b: calls[id(b)](), blocks, 100, 10, stream)
+            v, g, l = t.eval(blocks[0], out=o)
+            torch.cuda.synchronize()
+            got = {"val": v.cpu().numpy(), "grad": g.cpu().numpy(), "lap": l.cpu().numpy()}
+            err = {k: float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in ref}
+            rb = t.info()["row_bytes"]
+            shape = t.get_shape(1536)
+            out[f"{label}_{st}"] = {"kernel_us": tk * 1e6, "evals_per_s": 1536 * spec.norb / tk,
+                                   "row_bytes": rb, "max_rel_err": err,
+                                   "shape": {"tile_pos": shape[0], "vec": shape[1]}}
+            log(f"precision {label} {st}: {tk * 1e6:.1f} us, err val {err['val']:.1e} "
+                f"grad {err['grad']:.1e} lap {err['lap']:.1e}")
+            t.free()
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=5):
     """A plain device copy of known size (calibrates rocprof byte counters)."""
     import torch
@@ -307,6 +351,8 @@ def main():
     ap.add_argument("--save-tuning", default="",
                     help="write the shapes chosen by this run to this JSON file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the storage-dtype / complex k-point section")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving rate point")
     ap.add_argument("--copy-probe", action="store_true",
@@ -436,6 +482,14 @@ def main():
 
     if args.save_tuning:
         cache.save(args.save_tuning)
+
+    if not args.no_precision:
+        try:
+            result["precision"] = bench_precision(args, coef, spec, cache)
+            if args.save_tuning:
+                cache.save(args.save_tuning)
+        except Exception as e:
+            result["precision"] = {"error": f"{type(e).__name__}: {e}"}
 
     if not args.no_batched:
         try:

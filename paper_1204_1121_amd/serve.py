@@ -272,12 +272,18 @@ class GpuBackend:
     positions and offsets host-to-device on the slot's stream and replays the
     plan; an event marks completion.
 
+    Launches smaller than ``sort_threshold`` positions skip the spatial sort
+    and run one direct blip_eval on the slot's buffers (the host knows the
+    packed count); the sort pays only when many positions share rows.  Both
+    forms compute every output in the same order, so results are identical.
+
     batched=False runs one request per launch with ``kernel`` (e.g. the plain
     single-block kernel), the unbatched baseline.
     """
 
     def __init__(self, tables, capacity: int = 16384, max_requests: int = 512,
-                 slots_per_system: int = 2, batched: bool = True, kernel: str = "auto"):
+                 slots_per_system: int = 2, batched: bool = True, kernel: str = "auto",
+                 sort_threshold: int = 4096):
         import torch
         self.torch = torch
         self.tables = tables
@@ -285,6 +291,7 @@ class GpuBackend:
         self.slots_per_system = slots_per_system
         self.batched = batched
         self.kernel = kernel
+        self.sort_threshold = sort_threshold
         self._cap = capacity if batched else 1536
         self._maxr = max_requests if batched else 1
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -335,9 +342,12 @@ class GpuBackend:
             hoff[len(offs):].fill_(row)
         with torch.cuda.stream(sl["stream"]):
             sl["pos"][:row].copy_(hpos[:row], non_blocking=True)
-            if self.batched:
+            if self.batched and row >= self.sort_threshold:
                 sl["off"].copy_(hoff, non_blocking=True)
                 sl["plan"].launch(sl["stream"])
+            elif self.batched:
+                out = tuple(x[:row] for x in sl["out"])
+                self.tables[s].eval(sl["pos"][:row], out=out, stream=sl["stream"])
             else:
                 out = tuple(x[:row] for x in sl["out"])
                 self.tables[s].eval(sl["pos"][:row], out=out, kernel=self.kernel,

@@ -28,11 +28,12 @@ def systems():
         t.free()
 
 
-@pytest.mark.parametrize("batched", [True, False])
-def test_serving_mix_equals_alone(systems, batched):
+@pytest.mark.parametrize("batched,threshold", [(True, 4096), (True, 1), (False, 0)],
+                         ids=["batched", "batched-always-sorted", "unbatched-plain"])
+def test_serving_mix_equals_alone(systems, batched, threshold):
     specs, coefs, tables = systems
     be = GpuBackend(tables, capacity=4096, max_requests=64, batched=batched,
-                    kernel="auto" if batched else "plain")
+                    kernel="auto" if batched else "plain", sort_threshold=threshold)
     sv = Server(be, budget_bytes=64 << 20)
     reqs = wl.serving_requests(3, 300, rate=20000.0, specs=specs, seed=1, max_pos=600)
     sreqs = [ServeRequest(r.rid, r.system, r.pos, arrival=r.arrival, keep=True) for r in reqs]
