@@ -315,3 +315,51 @@ def test_complex_gamma_and_bloch_relation(blip):
     for key in y0:
         ref = ph * y0[key]
         assert np.max(np.abs(y1[key] - ref)) <= FP32_TOL * np.max(np.abs(ref)), key
+
+
+def test_values_only_complex_and_skewed(blip):
+    """Values-only kernels on a complex k-point table in a skewed cell, in
+    every storage dtype: equal to the values of the full kernel."""
+    rng = np.random.default_rng(41)
+    n = (10, 11, 12)
+    c = (rng.standard_normal(n + (20,)) + 1j * rng.standard_normal(n + (20,))).astype(np.complex64)
+    k = np.array([0.2, -0.3, 0.15])
+    pos = rng.uniform(-8, 12, (50, 3))
+    ref = oracle.evaluate(SKEW, n, c, pos, kvec=k, nthreads=4)
+    say("values-only, complex k-point, skewed cell")
+    for storage in ("c64", "cbf16", "cf16"):
+        t = blip.Table(SKEW, n, c, storage, kvec=k)
+        full = gpu_eval(t, pos)
+        vo = gpu_eval(t, pos, grad=False)
+        np.testing.assert_array_equal(vo["val"], full["val"])
+        tol = FP32_TOL if storage == "c64" else HALF_TOL
+        check(full, ref, tol, f"{storage} full")
+        pl = gpu_eval(t, pos, kernel="plain", grad=False)
+        check({"val": pl["val"]}, {"val": ref["val"]}, tol, f"{storage} plain values")
+        t.free()
+
+
+def test_concurrent_streams_share_a_table(small):
+    """Evaluations on two streams at once read the same immutable table; each
+    result equals the one computed alone."""
+    spec, c32, pos, t, ref, _ = small
+    rng = np.random.default_rng(5)
+    p1 = torch.from_numpy(rng.uniform(0, 10, (3000, 3))).cuda()
+    p2 = torch.from_numpy(rng.uniform(0, 10, (2000, 3))).cuda()
+    say("two streams on one table")
+    a1 = t.eval(p1)
+    a2 = t.eval(p2)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    o1 = t.alloc_outputs(3000)
+    o2 = t.alloc_outputs(2000)
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            t.eval(p1, out=o1, stream=s1)
+        with torch.cuda.stream(s2):
+            t.eval(p2, out=o2, stream=s2)
+    torch.cuda.synchronize()
+    for x, y in zip(o1, a1):
+        assert torch.equal(x, y)
+    for x, y in zip(o2, a2):
+        assert torch.equal(x, y)
