@@ -197,3 +197,29 @@ def evaluate(lattice, n, coef, pos, kvec=None, want=("val", "grad", "lap"),
     """Orbitals (and gradients, Laplacians) at every position, in FP64;
     see Oracle.evaluate."""
     return _oracle().evaluate(lattice, n, coef, pos, kvec=kvec, want=want, nthreads=nthreads)
+
+
+def ratio(lattice, n, coef, pos, inv_t, cols, want=("ratio", "grad", "lap"), nthreads: int = 1):
+    """Quasi-simultaneous acceptance ratios of the Slater part (Eq.
+    (11.12.23.1)) against the old inverse, for real orbitals, in FP64:
+
+        r_j      = sum_l psi_l(r'_j)      Dinv[l, c_j]
+        g_j      = sum_l grad psi_l(r'_j) Dinv[l, c_j]
+        lambda_j = sum_l lap psi_l(r'_j)  Dinv[l, c_j]
+
+    inv_t is the transposed inverse, inv_t[c, l] = Dinv[l, c] (the column of
+    electron c stored contiguously); cols[j] is the electron whose move
+    position j is.  r_j is det(D')/det(D) for D' = D with row c_j replaced by
+    the orbitals at r'_j; g_j / r_j and lambda_j / r_j are the gradient and
+    Laplacian of that ratio with respect to r'_j.
+    """
+    o = evaluate(lattice, n, coef, pos, want=tuple(
+        k for k in ("val", "grad", "lap") if (k == "val") or (k in want)), nthreads=nthreads)
+    cols = np.asarray(cols, dtype=np.int64)
+    w = np.asarray(inv_t, dtype=np.float64)[cols]              # [npos, L]
+    out = {"ratio": np.einsum("jl,jl->j", o["val"], w)}
+    if "grad" in want:
+        out["grad"] = np.einsum("jcl,jl->jc", o["grad"], w)
+    if "lap" in want:
+        out["lap"] = np.einsum("jl,jl->j", o["lap"], w)
+    return out
