@@ -13,6 +13,10 @@ Two independent formulations live here:
 * :mod:`oracle.brute` -- a NumPy brute force over *every* coefficient of a
   tiny grid and its periodic images, with the spline written in
   truncated-power form.  It pins the C oracle.
+* :func:`ratio` -- the quasi-simultaneous acceptance ratio of the Slater part,
+  the FP64 dot product of the orbitals with a column of the old inverse.
+* :mod:`oracle.slater` -- the sequential Sherman-Morrison update of the
+  inverse Slater matrix after accepted moves, in NumPy.
 
 Inputs are NumPy arrays; outputs are float64 (complex128 for complex tables).
 """
