@@ -351,6 +351,7 @@ def main():
     ap.add_argument("--save-tuning", default="",
                     help="write the shapes chosen by this run to this JSON file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--no-ratio", action="store_true", help="skip the fused-ratio figure")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the storage-dtype / complex k-point section")
     ap.add_argument("--serve-requests", type=int, default=10000,
@@ -463,6 +464,27 @@ def main():
                            "hbm_gbs": b_alg_mean / tp / 1e9,
                            "speedup_tuned_vs_plain": tp / t_kernel}
         log(f"plain: kernel {tp * 1e6:.1f} us")
+
+    if not args.no_ratio:
+        # fused acceptance ratios on the same blocks: two spins x 768
+        # electrons, one row of the (transposed) inverse per position
+        # (seeded synthetic rows: the timing does not depend on their values)
+        g = torch.Generator(device="cuda").manual_seed(wl.SEED_BASE)
+        inv_rows = torch.randn((npos, L), dtype=torch.float64, device="cuda", generator=g)
+        rout = (torch.empty(npos, dtype=torch.float64, device="cuda"),
+                torch.empty((npos, 3), dtype=torch.float64, device="cuda"),
+                torch.empty(npos, dtype=torch.float64, device="cuda"))
+
+        def ratio_step(pos):
+            table.ratio(pos, inv_rows, out=rout)
+        _, tr = time_region(ratio_step, blocks, args.steps, args.warmup, stream)
+        b_ratio = float(np.mean(U)) * row_bytes + npos * (24 + 40) + npos * L * 8
+        result["ratio"] = {"kernel_us": tr * 1e6, "evals_per_s": npos * L / tr,
+                           "bytes_algorithmic": b_ratio, "hbm_gbs": b_ratio / tr / 1e9,
+                           "frac": b_ratio / tr / 1e9 / HBM_PEAK_GBS,
+                           "outputs": "ratio + grad ratio + lap ratio per position (FP64)"}
+        log(f"ratio: {tr * 1e6:.1f} us per block (ratio, grad, lap) vs {t_kernel * 1e6:.1f} us "
+            f"for the orbitals")
 
     if not args.no_cold:
         # Cold Infinity Cache: read 1 GiB of unrelated data before every

@@ -9,7 +9,7 @@
  * the coefficient table resident on the GPU (loaded once, as the paper's
  * precomputed input file is) and evaluates psi_l, grad psi_l and
  * lap psi_l for all L orbitals at a block of positions -- the block of
- * trial moves that quasi-simultaneous updating (Sec. III.A, Eqs.
+ * trial moves that quasi-simultaneous updating (Sec. IV.A, Eqs.
  * (11.12.23.1)-(11.12.23.2)) produces once per Monte Carlo step.
  *
  * Conventions shared by every call:
@@ -65,7 +65,7 @@ enum {
     BLIP_E_OOM = -2,     /* device allocation failed                       */
     BLIP_E_HIP = -3,     /* a HIP runtime call failed                      */
     BLIP_E_DTYPE = -4,   /* dtype not valid for this table / request       */
-    BLIP_E_ALIGN = -5,   /* pointer not 16-byte aligned                    */
+    BLIP_E_ALIGN = -5,   /* pointer not aligned as the call requires       */
     BLIP_E_STATE = -6,   /* invalid handle or object state                 */
     BLIP_E_NODEV = -7    /* no usable gfx950 device                        */
 };
@@ -75,7 +75,7 @@ typedef enum {
     BLIP_KERNEL_AUTO = 0,   /* tuned tiled kernel (what blip_eval runs)        */
     BLIP_KERNEL_PLAIN = 1,  /* one workgroup per position, one lane per orbital,
                                64 x 5 weights in LDS: the paper's coalesced
-                               mapping (Sec. III.B) written for wave64         */
+                               mapping (Sec. IV.B) written for wave64         */
     BLIP_KERNEL_TILED = 2,  /* P positions per workgroup, separable 1-D weights,
                                o orbitals per lane with wide loads             */
     BLIP_KERNEL_F64ACC = 3  /* tiled kernel with FP64 weights, accumulation and
@@ -119,7 +119,7 @@ BLIP_API int blip_load(const double lattice[9], int n1, int n2, int n3,
 /*
  * blip_eval -- evaluate all orbitals at a block of positions (Eq.
  * (11.12.24.1) for every j of the block; the N x L independent evaluations
- * of quasi-simultaneous updating, Sec. III.A).
+ * of quasi-simultaneous updating, Sec. IV.A).
  *
  *  t     handle from blip_load.
  *  pos   device double[npos][3], Cartesian bohr, any values (wrapped in FP64).
@@ -152,7 +152,7 @@ BLIP_API int blip_eval_ex(blip_table t, const double* pos, int64_t npos,
 /*
  * blip_eval_batched -- evaluate the move blocks of many walkers in one
  * persistent launch (quasi-simultaneous updating makes every moved electron
- * of every walker an independent evaluation, Sec. III.A, Eq. (11.12.23.1)).
+ * of every walker an independent evaluation, Sec. IV.A, Eq. (11.12.23.1)).
  *
  *  pos       device double[capacity][3]: the walkers' blocks concatenated;
  *            walker w owns rows offsets[w] .. offsets[w+1]-1.
@@ -224,6 +224,95 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
  * cached autotuning result. */
 BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec);
 BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec);
+
+/*
+ * blip_eval_ratio -- quasi-simultaneous acceptance ratios of the Slater part
+ * (Eq. (11.12.23.1)) against the old inverse, fused into the evaluation so
+ * that N numbers are written instead of N x L orbitals (real tables only):
+ *
+ *   ratio[j]         = sum_l psi_l(r'_j)      Dinv[l, c_j]
+ *   grad_ratio[j][:] = sum_l grad psi_l(r'_j) Dinv[l, c_j]
+ *   lap_ratio[j]     = sum_l lap psi_l(r'_j)  Dinv[l, c_j]
+ *
+ * ratio[j] is det(D')/det(D) for the Slater matrix D[i][l] = psi_l(r_i) with
+ * row c_j replaced by the orbitals at the trial position r'_j; grad_ratio/ratio
+ * and lap_ratio/ratio are its gradient and Laplacian in r'_j.
+ *
+ *  pos        device double[npos][3] trial positions (as blip_eval).
+ *  inv_rows   device double: row r at inv_rows + r * inv_ld holds
+ *             Dinv[l, c] for l = 0..L-1 (a column of the inverse, stored as a
+ *             row: the transposed inverse); inv_ld >= L.
+ *  row_of     device int64[npos]: the row position j uses (NULL: row j).
+ *  ratio      device double[npos]; grad_ratio [npos][3] and lap_ratio [npos]
+ *             device doubles, both or neither (NULL: values-only kernel).
+ * The orbitals are summed in FP32 exactly as blip_eval does; the dot products
+ * with the inverse are FP64 in a fixed order.  Pointers 8-byte aligned.
+ * BLIP_E_DTYPE for complex tables; BLIP_E_ARG if L exceeds 16 lane chunks
+ * (4,096 orbitals in FP32).  Asynchronous on the stream, no allocation.
+ */
+BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
+                             const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
+                             double* ratio, double* grad_ratio, double* lap_ratio,
+                             void* stream);
+
+/*
+ * blip_eval_ratio_batched -- blip_eval_ratio for many walkers in one
+ * persistent launch: positions concatenated and offsets as in
+ * blip_eval_batched (only offsets[nw] is read, on the device), row_of[j]
+ * (NULL: row j) selecting each position's row of the stacked transposed
+ * inverses of all walkers; ratio outputs have capacity rows, of which the
+ * first offsets[nw] are written.  Same workspace as blip_eval_batched.
+ */
+BLIP_API int blip_eval_ratio_batched(blip_table t, const double* pos, const int64_t* offsets,
+                                     int nw, int64_t capacity, const double* inv_rows,
+                                     int64_t inv_ld, const int64_t* row_of, double* ratio,
+                                     double* grad_ratio, double* lap_ratio, void* workspace,
+                                     size_t workspace_bytes, void* stream);
+
+/*
+ * blip_sm_update -- bring the inverse Slater matrix up to date after the
+ * accepted moves of a step (Sec. VI.D; the Slater matrix of Eq. (5)):
+ * the moves are applied in the given order, each as the Sherman-Morrison
+ * rank-1 update of one electron's row.
+ *
+ * Conventions are those of blip_eval_ratio: D[i][l] = psi_l(r_i), one
+ * electron per row, and the inverse is held transposed, B[i][l] = Dinv[l][i]
+ * (the column of Dinv that electron i pairs with, stored as a row).  Moving
+ * electron c replaces row c of D by u[l] = psi_l(r'_c); then
+ *   ratio  = sum_l u[l] B[c][l],      v_i = sum_l u[l] B[i][l],
+ *   B'[c]  = B[c] / ratio,            B'[i] = B[i] - (v_i / ratio) B[c]  (i != c).
+ *
+ *  n          matrix order (electrons of one spin = orbitals), 1..4096.
+ *  inv        device double, B with row i at inv + i * inv_ld; updated in place.
+ *  u          device float [u_nrows][u_ld], u_ld >= n: the new orbital rows
+ *             (columns l < n are read) -- typically the val output of
+ *             blip_eval for the step's trial positions.
+ *  cols       HOST int64[k]: the accepted electrons, in the order the moves
+ *             are applied; an electron may appear more than once.
+ *  u_row      HOST int64[k] or NULL: the row of u holding move m's new
+ *             orbitals (NULL: row cols[m], i.e. u ordered by electron).
+ *  ratios     device double[k] or NULL: ratios[m] = det(D^(m)) / det(D^(m-1)),
+ *             the ratio of move m against the matrix that already holds moves
+ *             0..m-1 (so their product is det(D_new) / det(D_old)).
+ *  workspace  device memory of blip_sm_workspace_size(n) bytes, 8-byte aligned,
+ *             not shared with another call in flight.
+ * Computed in FP64 (u converted exactly).  Up to 32 consecutive moves are
+ * applied per launch in the equivalent rank-k (Woodbury) form, eliminating
+ * the k x k block of moved rows without pivoting in move order -- the same
+ * divisions by the sequential ratios the rank-1 updates make, so a ratio of
+ * zero yields non-finite rows exactly as the rank-1 form would.
+ * Asynchronous on the stream, no allocation; ceil(k/32)+1 launches (about
+ * one more per repeated electron).  k = 0 enqueues nothing.  BLIP_E_ARG for
+ * a size or index out of range, BLIP_E_ALIGN for misaligned pointers.
+ */
+BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float* u,
+                            int64_t u_nrows, int64_t u_ld, const int64_t* cols,
+                            const int64_t* u_row, int64_t k, double* ratios, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/* blip_sm_workspace_size -- bytes of workspace blip_sm_update needs for
+ * order n (0 if n is out of range). */
+BLIP_API size_t blip_sm_workspace_size(int64_t n);
 
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */

@@ -81,6 +81,16 @@ def lib() -> ctypes.CDLL:
     L.blip_set_shape.argtypes = [vp, ci, i64, ci, ci]
     L.blip_get_shape.restype = ci
     L.blip_get_shape.argtypes = [vp, ci, i64, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.blip_eval_ratio.restype = ci
+    L.blip_eval_ratio.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+    L.blip_eval_ratio_batched.restype = ci
+    L.blip_eval_ratio_batched.argtypes = [vp, vp, vp, ci, i64, vp, i64, vp, vp, vp, vp, vp,
+                                          ctypes.c_size_t, vp]
+    L.blip_sm_update.restype = ci
+    L.blip_sm_update.argtypes = [i64, vp, i64, vp, i64, i64, vp, vp, i64, vp, vp,
+                                 ctypes.c_size_t, vp]
+    L.blip_sm_workspace_size.restype = ctypes.c_size_t
+    L.blip_sm_workspace_size.argtypes = [i64]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -198,6 +208,48 @@ class Table:
                 raise BlipError(rc, err().decode())
         return call
 
+    # -- fused acceptance ratios ---------------------------------------------
+
+    def ratio(self, pos: torch.Tensor, inv_rows: torch.Tensor, row_of=None,
+              grad: bool = True, out=None, stream=None):
+        """Acceptance ratios against the old inverse (blip_eval_ratio).
+        inv_rows: cuda float64 [nrows, >= L], row r = column of D^{-1};
+        row_of: cuda int64 [npos] or None (row j for position j).
+        Returns (ratio [npos], grad [npos, 3] or None, lap [npos] or None)."""
+        if inv_rows.dtype != torch.float64 or inv_rows.dim() != 2 or inv_rows.stride(1) != 1:
+            raise ValueError("inv_rows must be a float64 CUDA matrix with unit column stride")
+        npos = pos.shape[0]
+        if out is None:
+            dev = pos.device
+            r = torch.empty(npos, dtype=torch.float64, device=dev)
+            g = torch.empty((npos, 3), dtype=torch.float64, device=dev) if grad else None
+            l = torch.empty(npos, dtype=torch.float64, device=dev) if grad else None
+            out = (r, g, l)
+        r, g, l = out
+        check(lib().blip_eval_ratio(self.handle, _ptr(pos), npos, _ptr(inv_rows),
+                                    inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(g),
+                                    _ptr(l), _stream_ptr(stream)))
+        return r, g, l
+
+    def ratio_batched(self, pos, offsets, inv_rows, row_of=None, grad: bool = True, out=None,
+                      workspace=None, capacity: int | None = None, stream=None):
+        """blip_eval_ratio_batched: ratios for concatenated walker blocks."""
+        cap = pos.shape[0] if capacity is None else int(capacity)
+        if out is None:
+            dev = pos.device
+            out = (torch.empty(cap, dtype=torch.float64, device=dev),
+                   torch.empty((cap, 3), dtype=torch.float64, device=dev) if grad else None,
+                   torch.empty(cap, dtype=torch.float64, device=dev) if grad else None)
+        if workspace is None:
+            workspace = self.workspace(cap, pos.device)
+        r, g, l = out
+        check(lib().blip_eval_ratio_batched(self.handle, _ptr(pos), _ptr(offsets),
+                                            int(offsets.shape[0]) - 1, cap, _ptr(inv_rows),
+                                            inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(g),
+                                            _ptr(l), _ptr(workspace), workspace.numel(),
+                                            _stream_ptr(stream)))
+        return r, g, l
+
     # -- batched walker blocks -------------------------------------------
 
     def workspace_bytes(self, capacity: int) -> int:
@@ -310,6 +362,43 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+def sm_workspace(n: int, device="cuda") -> torch.Tensor:
+    """Workspace for sm_update on order-n matrices (blip_sm_workspace_size)."""
+    nbytes = lib().blip_sm_workspace_size(int(n))
+    if nbytes == 0:
+        raise ValueError(f"n = {n} is out of range for blip_sm_update")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def sm_update(inv: torch.Tensor, u: torch.Tensor, cols, u_row=None, ratios=None,
+              workspace=None, stream=None):
+    """Sherman-Morrison update of the transposed inverse in place
+    (blip_sm_update).  inv: cuda float64 [n, >= n] with unit column stride,
+    row i = column i of D^{-1}; u: cuda float32 [rows, >= n], the new orbital
+    rows; cols: host sequence of accepted electrons in move order; u_row: host
+    sequence of the row of u each move reads (None: row cols[m]).  Returns the
+    sequential ratios (cuda float64 [k])."""
+    n = inv.shape[0]
+    if inv.dtype != torch.float64 or inv.dim() != 2 or inv.stride(1) != 1 or inv.shape[1] < n:
+        raise ValueError("inv must be a float64 CUDA matrix [n, >= n] with unit column stride")
+    if u.dtype != torch.float32 or u.dim() != 2 or u.stride(1) != 1 or u.shape[1] < n:
+        raise ValueError("u must be a float32 CUDA matrix [rows, >= n] with unit column stride")
+    c = np.ascontiguousarray(np.asarray(cols, dtype=np.int64).reshape(-1))
+    ur = None if u_row is None else np.ascontiguousarray(np.asarray(u_row, dtype=np.int64).reshape(-1))
+    if ur is not None and ur.shape != c.shape:
+        raise ValueError("u_row needs one entry per move")
+    if ratios is None:
+        ratios = torch.empty(c.size, dtype=torch.float64, device=inv.device)
+    if workspace is None:
+        workspace = sm_workspace(n, inv.device)
+    check(lib().blip_sm_update(n, _ptr(inv), inv.stride(0), _ptr(u), u.shape[0], u.stride(0),
+                               c.ctypes.data_as(ctypes.c_void_p),
+                               None if ur is None else ur.ctypes.data_as(ctypes.c_void_p),
+                               c.size, _ptr(ratios), _ptr(workspace), workspace.numel(),
+                               _stream_ptr(stream)))
+    return ratios
 
 
 def version() -> str:

@@ -3,7 +3,7 @@
 // launch-shape autotuner.
 //
 // Quasi-simultaneous updating makes every moved electron of every walker an
-// independent evaluation against the same table (Sec. III.A, Eq.
+// independent evaluation against the same table (Sec. IV.A, Eq.
 // (11.12.23.1)), so a batch of walker blocks is evaluated as one
 // concatenated set of positions; the offsets only delimit walkers for the
 // caller.  Sorting the concatenation by space lets positions that share
@@ -33,6 +33,7 @@ struct SortArgs {
     int* cursor;             // [nbins]
     int* keys;               // [capacity]
     int* perm;               // [capacity]
+    double* spos;            // [capacity][3]: positions in slot order
 };
 
 constexpr int kMaxBins = 16384;
@@ -119,6 +120,9 @@ __global__ void scatter_kernel(const KArgs a, SortArgs s)
          j += (int64_t)gridDim.x * blockDim.x) {
         const int slot = atomicAdd(&s.cursor[s.keys[j]], 1);
         s.perm[slot] = (int)j;
+        s.spos[3 * (int64_t)slot] = a.pos[3 * j];
+        s.spos[3 * (int64_t)slot + 1] = a.pos[3 * j + 1];
+        s.spos[3 * (int64_t)slot + 2] = a.pos[3 * j + 2];
     }
 }
 
@@ -128,7 +132,7 @@ __global__ void scatter_kernel(const KArgs a, SortArgs s)
 
 struct SortLayout {
     int nbins;
-    size_t off_counts, off_cursor, off_keys, off_perm, total;
+    size_t off_counts, off_cursor, off_keys, off_perm, off_spos, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -146,6 +150,8 @@ static SortLayout sort_layout(const blip_table_s* t, int64_t capacity)
     off = align256(off + sizeof(int) * (size_t)std::max<int64_t>(capacity, 1));
     L.off_perm = off;
     off = align256(off + sizeof(int) * (size_t)std::max<int64_t>(capacity, 1));
+    L.off_spos = off;
+    off = align256(off + 3 * sizeof(double) * (size_t)std::max<int64_t>(capacity, 1));
     L.total = off;
     return L;
 }
@@ -180,7 +186,8 @@ static int grid_blocks(int64_t n, int per, int cap)
 // Enqueue fill -> bin -> scan -> scatter -> persistent evaluation on s.
 static int enqueue_batched(const blip_table_s* t, const double* pos, const int64_t* offsets,
                            int nw, int64_t capacity, void* val, void* grad, void* lap,
-                           void* workspace, int P, int OE, hipStream_t s)
+                           void* workspace, int P, int OE, hipStream_t s,
+                           const RatioArgs* ratio = nullptr)
 {
     const SortLayout L = sort_layout(t, capacity);
     char* ws = static_cast<char*>(workspace);
@@ -194,6 +201,7 @@ static int enqueue_batched(const blip_table_s* t, const double* pos, const int64
     sa.cursor = reinterpret_cast<int*>(ws + L.off_cursor);
     sa.keys = reinterpret_cast<int*>(ws + L.off_keys);
     sa.perm = reinterpret_cast<int*>(ws + L.off_perm);
+    sa.spos = reinterpret_cast<double*>(ws + L.off_spos);
     KArgs a;
     fill_table_args(t, a);
     a.pos = pos;
@@ -220,8 +228,8 @@ static int enqueue_batched(const blip_table_s* t, const double* pos, const int64
     // every XCD's tile range has workgroups, never many more than tiles
     int grid = grid_blocks(capacity, P, 4 * std::max(1, t->ncu));
     grid = std::max(8, (grid + 7) / 8 * 8);
-    return launch_tiled(t, pos, capacity, val, grad, lap, KIND_TILED, P, OE, sa.perm,
-                        offsets + nw, sa.counts + L.nbins, grid, true, s);
+    return launch_tiled(t, pos, capacity, val, grad, lap, KIND_TILED, P, OE, sa.perm, sa.spos,
+                        offsets + nw, sa.counts + L.nbins, grid, true, s, ratio);
 }
 
 static int batched_shape(const blip_table_s* t, int64_t capacity, int& P, int& OE)
@@ -264,6 +272,33 @@ BLIP_API int blip_eval_batched(blip_table t, const double* pos, const int64_t* o
     batched_shape(t, capacity, P, OE);
     return enqueue_batched(t, pos, offsets, nw, capacity, val, grad, lap, workspace, P, OE,
                            static_cast<hipStream_t>(stream));
+}
+
+BLIP_API int blip_eval_ratio_batched(blip_table t, const double* pos, const int64_t* offsets,
+                                     int nw, int64_t capacity, const double* inv_rows,
+                                     int64_t inv_ld, const int64_t* row_of, double* ratio,
+                                     double* grad_ratio, double* lap_ratio, void* workspace,
+                                     size_t workspace_bytes, void* stream)
+{
+    int rc = check_ratio_args(t, capacity, pos, inv_rows, inv_ld, row_of, ratio, grad_ratio,
+                              lap_ratio);
+    if (rc != BLIP_OK) return rc;
+    if (nw < 0) return fail(BLIP_E_ARG, "nw must be >= 0 (got %d)", nw);
+    if (nw == 0 || capacity == 0) return BLIP_OK;
+    if (offsets == nullptr || (reinterpret_cast<uintptr_t>(offsets) & 7u) != 0)
+        return fail(BLIP_E_ARG, "offsets must be non-NULL and 8-byte aligned");
+    const SortLayout L = sort_layout(t, capacity);
+    if (workspace == nullptr || workspace_bytes < L.total)
+        return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", L.total,
+                    workspace_bytes);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return fail(BLIP_E_ALIGN, "workspace must be 256-byte aligned");
+    int P = 0, OE = 0;
+    rc = ratio_shape(t, MODE_BATCHED, capacity, P, OE);
+    if (rc != BLIP_OK) return rc;
+    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, grad_ratio, lap_ratio};
+    return enqueue_batched(t, pos, offsets, nw, capacity, nullptr, nullptr, nullptr, workspace, P,
+                           OE, static_cast<hipStream_t>(stream), &ra);
 }
 
 BLIP_API int blip_plan_create(blip_table t, const double* pos, const int64_t* offsets, int nw,
@@ -368,7 +403,7 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
                 rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap, workspace,
                                                P, OE, s)
                              : launch_tiled(t, pb, npos, val, grad, lap, KIND_TILED, P, OE,
-                                            nullptr, nullptr, nullptr, 0, false, s);
+                                            nullptr, nullptr, nullptr, nullptr, 0, false, s);
                 (void)hipEventRecord(e1, s);
                 e = hipEventSynchronize(e1);
                 if (e != hipSuccess) rc = fail_hip(e, "autotune sync");

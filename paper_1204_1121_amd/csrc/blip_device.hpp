@@ -6,7 +6,7 @@
 //   psi_l(r_j) = sum_s a_{l,s} Theta_s(r_j)
 // plus its Cartesian gradient and Laplacian.  The table is stored with the
 // orbital index fastest (Sec. II.B: the orbital index is the contiguous one,
-// which the coalesced mapping of Sec. III.B relies on).
+// which the coalesced mapping of Sec. IV.B relies on).
 //
 // Two kernel families live here:
 //   * plain_kernel: one workgroup per position, one lane per orbital, the 64
@@ -58,8 +58,17 @@ struct KArgs {
     const double* pos;       // [npos][3]
     int64_t npos;
     const int* perm;         // optional: slot -> original position index
+    const double* spos;      // optional: positions already in slot order [npos][3]
     const int64_t* dev_count;// optional: device-side npos (persistent launch)
     int* xcd_next;           // persistent launch: next-tile counter per XCD (8)
+    // acceptance-ratio epilogue (real tables): dot with rows of the
+    // transposed inverse Slater matrix instead of storing the orbitals
+    const double* inv_rows;  // row r at inv_rows + r * inv_ld, L entries
+    int64_t inv_ld;
+    const int64_t* row_of;   // position j uses row row_of[j] (NULL: row j)
+    double* ratio;           // [npos]
+    double* gratio;          // [npos][3] or NULL
+    double* lratio;          // [npos] or NULL
     void* val;               // [npos][W] float (double for FP64 accumulation)
     void* grad;              // [npos][3][W]
     void* lap;               // [npos][W]
@@ -136,9 +145,9 @@ __device__ __forceinline__ void spline_weights(double f, double w[4],
 // Prepare one position: wrap, weights (metric folded in for orthorhombic
 // cells), row indices of the 4x4x4 stencil, Bloch phase.
 template <class WT, bool ORTHO, bool BLOCH>
-__device__ void prep_position(const KArgs& a, const double* rp, PosPrep<WT>& pp)
+__device__ void prep_position(const KArgs& a, const double (&rin)[3], PosPrep<WT>& pp)
 {
-    double r[3] = {rp[0], rp[1], rp[2]};
+    double r[3] = {rin[0], rin[1], rin[2]};
     bool bad = false;
     int i0[3];
     double f[3];
@@ -566,11 +575,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 // Tiled kernel.  blockDim.x = 64 * nwaves (<= 256); one tile per workgroup,
 // or, when a device-side position count is given (a.dev_count), a persistent
 // loop over tiles whose number is only known on the device.
-template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC>
+constexpr int kRatioTile = 16;     // largest P with the ratio epilogue
+constexpr int kRatioChunks = 16;   // largest number of orbital chunks with it
+
+template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC, bool RATIO = false>
 __global__ void __launch_bounds__(kMaxThreads)
 tiled_kernel(const KArgs a)
 {
     __shared__ PosPrep<ACC> prep[kMaxTile];
+    constexpr int NR = FULL ? 5 : 1;
+    __shared__ double part[RATIO ? kRatioTile : 1][RATIO ? kRatioChunks : 1][NR];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -598,27 +612,45 @@ tiled_kernel(const KArgs a)
     const int xcd_begin = x * tq + (x < tr ? x : tr);
     const int xcd_end = xcd_begin + tq + (x < tr ? 1 : 0);
     __shared__ int s_next;
+    const int tile_end = persist ? xcd_end : ntiles;
+
+    // Positions of the next tile are loaded into registers (threads p < P)
+    // before the current tile's items run, so the prologue of the next tile
+    // does not wait on memory while the workgroup's wavefronts idle.
+    double nr[3] = {0.0, 0.0, 0.0};
+    auto fetch = [&](int tl) {
+        const int64_t j = (int64_t)tl * P + threadIdx.x;
+        if ((int)threadIdx.x < P && tl < tile_end && j < npos) {
+            const double* rp = a.spos ? a.spos + 3 * j
+                                      : a.pos + 3 * (a.perm ? (int64_t)a.perm[j] : j);
+            nr[0] = rp[0];
+            nr[1] = rp[1];
+            nr[2] = rp[2];
+        }
+    };
+    int tile;
+    if (persist) {
+        if (threadIdx.x == 0) s_next = atomicAdd(&a.xcd_next[x], 1);
+        __syncthreads();
+        tile = xcd_begin + s_next;
+        __syncthreads();   // all threads have read s_next
+    } else {
+        tile = xcd_tile(blockIdx.x, ntiles);
+    }
+    fetch(tile);
 
     for (int it = 0;; ++it) {
-        int tile;
-        if (persist) {
-            __syncthreads();   // previous tile's readers are done with prep[] and s_next
-            if (threadIdx.x == 0) s_next = atomicAdd(&a.xcd_next[x], 1);
-            __syncthreads();
-            tile = xcd_begin + s_next;
-            if (tile >= xcd_end) break;
-        } else {
-            if (it > 0) break;
-            tile = xcd_tile(blockIdx.x, ntiles);
-        }
+        if (persist ? tile >= xcd_end : it > 0) break;
         const int64_t j0 = (int64_t)tile * P;
         const int np = (int)((npos - j0) < P ? (npos - j0) : P);
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int64_t slot = j0 + p;
-            const int64_t jo = a.perm ? (int64_t)a.perm[slot] : slot;
-            prep_position<ACC, ORTHO, BLOCH>(a, a.pos + 3 * jo, prep[p]);
+        if ((int)threadIdx.x < np) prep_position<ACC, ORTHO, BLOCH>(a, nr, prep[threadIdx.x]);
+        if (persist && threadIdx.x == 0) s_next = atomicAdd(&a.xcd_next[x], 1);
+        __syncthreads();   // prep[] and s_next are visible
+        int next = tile + 1;
+        if (persist) {
+            next = xcd_begin + s_next;
+            fetch(next);
         }
-        __syncthreads();
 
         const int items = np * C;
         for (int item = wave; item < items; item += nwaves) {
@@ -660,6 +692,34 @@ tiled_kernel(const KArgs a)
 #pragma unroll
                     for (int e = 0; e < OE; ++e) res[q][e] = (ACC)__builtin_nan("");
             }
+            if constexpr (RATIO) {
+                // this chunk's share of sum_l y_l Dinv[l, c]: per lane, then a
+                // fixed butterfly over the wavefront (the same order always)
+                double dot[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) dot[q] = 0.0;
+                if (lane_ok) {
+                    const int64_t r = a.row_of ? a.row_of[jo] : jo;
+                    const double* ir = a.inv_rows + r * a.inv_ld + e0;
+#pragma unroll
+                    for (int e = 0; e < OE; ++e) {
+                        if (e0 + e < W) {
+                            const double w = ir[e];
+#pragma unroll
+                            for (int q = 0; q < NR; ++q) dot[q] = fma_((double)res[q][e], w, dot[q]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) dot[q] += __shfl_xor(dot[q], off, kWave);
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) part[p][ch][q] = dot[q];
+                }
+                continue;   // nothing else is stored for this item
+            }
             if (lane_ok) {
                 const bool vec = a.vec_store != 0;
                 ACC* val = static_cast<ACC*>(a.val);
@@ -673,6 +733,30 @@ tiled_kernel(const KArgs a)
                 }
             }
         }
+        __syncthreads();   // all readers are done with prep[] and s_next
+        if constexpr (RATIO) {
+            // chunks summed in order; then the next tile may rewrite part[]
+            if ((int)threadIdx.x < np) {
+                const int p = threadIdx.x;
+                const int64_t slot = j0 + p;
+                const int64_t jo = a.perm ? (int64_t)a.perm[slot] : slot;
+                double t[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) t[q] = 0.0;
+                for (int ch = 0; ch < C; ++ch)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) t[q] += part[p][ch][q];
+                a.ratio[jo] = t[0];
+                if constexpr (FULL) {
+                    a.gratio[3 * jo] = t[1];
+                    a.gratio[3 * jo + 1] = t[2];
+                    a.gratio[3 * jo + 2] = t[3];
+                    a.lratio[jo] = t[4];
+                }
+            }
+            __syncthreads();
+        }
+        tile = next;
     }
 }
 

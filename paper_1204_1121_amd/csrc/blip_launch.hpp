@@ -25,6 +25,50 @@ template <class E>
 hipError_t launch_quantize(const float* src, char* dst, int64_t nrows, int W,
                            int64_t row_bytes, float scale, hipStream_t s);
 
+// Tiled kernel with the acceptance-ratio epilogue (real tables).
+template <class E>
+hipError_t launch_ratio(const KArgs& a, const Cfg& c, hipStream_t s);
+
+namespace detail {
+
+template <class E, int OE, bool FULL, bool ORTHO>
+hipError_t go_ratio(const KArgs& a, const Cfg& c, hipStream_t s)
+{
+    hipLaunchKernelGGL((tiled_kernel<E, OE, FULL, ORTHO, false, float, true>), dim3(c.grid),
+                       dim3(kWave * c.nwaves), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class E, int OE>
+hipError_t ratio_flags(const KArgs& a, const Cfg& c, hipStream_t s)
+{
+    if (c.full) return c.ortho ? go_ratio<E, OE, true, true>(a, c, s) : go_ratio<E, OE, true, false>(a, c, s);
+    return c.ortho ? go_ratio<E, OE, false, true>(a, c, s) : go_ratio<E, OE, false, false>(a, c, s);
+}
+
+}  // namespace detail
+
+template <class E>
+hipError_t launch_ratio(const KArgs& a, const Cfg& c, hipStream_t s)
+{
+    using namespace detail;
+    if constexpr (E::bytes == 4) {
+        switch (c.OE) {
+        case 1: return ratio_flags<E, 1>(a, c, s);
+        case 2: return ratio_flags<E, 2>(a, c, s);
+        case 4: return ratio_flags<E, 4>(a, c, s);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (c.OE) {
+        case 2: return ratio_flags<E, 2>(a, c, s);
+        case 4: return ratio_flags<E, 4>(a, c, s);
+        case 8: return ratio_flags<E, 8>(a, c, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
 namespace detail {
 
 template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC>

@@ -3,6 +3,7 @@
 
 namespace blip {
 template hipError_t launch_eval<F16>(const KArgs&, const Cfg&, hipStream_t);
+template hipError_t launch_ratio<F16>(const KArgs&, const Cfg&, hipStream_t);
 template hipError_t launch_quantize<F16>(const float*, char*, int64_t, int, int64_t, float,
                                           hipStream_t);
 }  // namespace blip

@@ -191,8 +191,9 @@ void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t
 }
 
 int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
-                 void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
-                 int* xcd_next, int grid, bool chunk_major, hipStream_t s)
+                 void* lap, int kind, int P, int OE, const int* perm, const double* spos,
+                 const int64_t* dev_count, int* xcd_next, int grid, bool chunk_major,
+                 hipStream_t s, const RatioArgs* ratio)
 {
     KArgs a;
     fill_table_args(t, a);
@@ -202,15 +203,74 @@ int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* v
     a.grad = grad;
     a.lap = lap;
     a.perm = perm;
+    a.spos = spos;
     a.dev_count = dev_count;
     a.xcd_next = xcd_next;
     a.chunk_major = chunk_major ? 1 : 0;
     const int64_t ntiles = (npos + P - 1) / P;
     a.ntiles = (int)ntiles;
     Cfg c;
+    if (ratio) {
+        a.inv_rows = ratio->inv_rows;
+        a.inv_ld = ratio->inv_ld;
+        a.row_of = ratio->row_of;
+        a.ratio = ratio->ratio;
+        a.gratio = ratio->gratio;
+        a.lratio = ratio->lratio;
+        make_cfg(t, kind, P, OE, ratio->gratio != nullptr, dev_count ? grid : ntiles, c, a);
+        hipError_t e;
+        switch (t->elem) {
+        case ELEM_F32: e = launch_ratio<F32>(a, c, s); break;
+        case ELEM_BF16: e = launch_ratio<BF16>(a, c, s); break;
+        default: e = launch_ratio<F16>(a, c, s); break;
+        }
+        if (e != hipSuccess) return fail_hip(e, "ratio kernel launch");
+        return BLIP_OK;
+    }
     make_cfg(t, kind, P, OE, grad != nullptr, dev_count ? grid : ntiles, c, a);
     hipError_t e = dispatch(t, a, c, s);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return BLIP_OK;
+}
+
+int check_ratio_args(blip_table t, int64_t npos, const double* pos, const double* inv_rows,
+                     int64_t inv_ld, const int64_t* row_of, double* ratio, double* grad_ratio,
+                     double* lap_ratio)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (t->complex_) return fail(BLIP_E_DTYPE, "acceptance ratios need a real table");
+    if (npos < 0) return fail(BLIP_E_ARG, "npos must be >= 0 (got %lld)", (long long)npos);
+    if ((grad_ratio == nullptr) != (lap_ratio == nullptr))
+        return fail(BLIP_E_ARG, "pass both grad_ratio and lap_ratio, or neither");
+    if (inv_ld < t->L)
+        return fail(BLIP_E_ARG, "inv_ld (%lld) must be >= norb (%d)", (long long)inv_ld, t->L);
+    if (npos == 0) return BLIP_OK;
+    if (npos > (int64_t)INT32_MAX) return fail(BLIP_E_ARG, "npos too large");
+    if (pos == nullptr || inv_rows == nullptr || ratio == nullptr)
+        return fail(BLIP_E_ARG, "pos, inv_rows and ratio must be non-NULL when npos > 0");
+    auto al8 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 7u) == 0; };
+    if (!al8(pos) || !al8(inv_rows) || !al8(ratio) || (row_of && !al8(row_of)) ||
+        (grad_ratio && (!al8(grad_ratio) || !al8(lap_ratio))))
+        return fail(BLIP_E_ALIGN,
+                    "pos, inv_rows, row_of and the ratio outputs must be 8-byte aligned");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != t->device)
+        return fail(BLIP_E_STATE, "table lives on device %d but device %d is current", t->device,
+                    dev);
+    return BLIP_OK;
+}
+
+int ratio_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
+{
+    choose_shape(t, mode, npos, P, OE);
+    P = std::min(P, kRatioTile);
+    // the epilogue keeps one partial sum per orbital chunk in LDS
+    auto chunks = [&](int o) { return (t->W + kWave * o - 1) / (kWave * o); };
+    while (chunks(OE) > kRatioChunks && valid_oe(t, OE * 2)) OE *= 2;
+    if (chunks(OE) > kRatioChunks)
+        return fail(BLIP_E_ARG, "norb %d too large for the ratio kernel", t->L);
     return BLIP_OK;
 }
 
@@ -284,8 +344,8 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
         if (e != hipSuccess) return fail_hip(e, "kernel launch");
         return BLIP_OK;
     }
-    return launch_tiled(t, pos, npos, val, grad, lap, kind, P, OE, nullptr, nullptr, nullptr, 0,
-                        false, static_cast<hipStream_t>(stream));
+    return launch_tiled(t, pos, npos, val, grad, lap, kind, P, OE, nullptr, nullptr, nullptr,
+                        nullptr, 0, false, static_cast<hipStream_t>(stream), nullptr);
 }
 
 }  // namespace blip
@@ -426,6 +486,21 @@ BLIP_API int blip_eval_ex(blip_table t, const double* pos, int64_t npos, void* v
                           void* lap, const blip_eval_opts* opts, void* stream)
 {
     return eval_common(t, pos, npos, val, grad, lap, opts, stream);
+}
+
+BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
+                             const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
+                             double* ratio, double* grad_ratio, double* lap_ratio, void* stream)
+{
+    int rc = check_ratio_args(t, npos, pos, inv_rows, inv_ld, row_of, ratio, grad_ratio,
+                              lap_ratio);
+    if (rc != BLIP_OK || npos == 0) return rc;
+    int P = 0, OE = 0;
+    rc = ratio_shape(t, MODE_BLOCK, npos, P, OE);
+    if (rc != BLIP_OK) return rc;
+    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, grad_ratio, lap_ratio};
+    return launch_tiled(t, pos, npos, nullptr, nullptr, nullptr, KIND_TILED, P, OE, nullptr,
+                        nullptr, nullptr, nullptr, 0, false, static_cast<hipStream_t>(stream), &ra);
 }
 
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage, int64_t* row_bytes,

@@ -21,6 +21,16 @@ struct TuneEntry {
     int P, OE;
 };
 
+// Acceptance-ratio epilogue arguments (blip_eval_ratio*).
+struct RatioArgs {
+    const double* inv_rows;
+    int64_t inv_ld;
+    const int64_t* row_of;
+    double* ratio;
+    double* gratio;
+    double* lratio;
+};
+
 // Launch-shape tables kept per table: single blocks, and sorted batches.
 enum TuneMode { MODE_BLOCK = 0, MODE_BATCHED = 1 };
 
@@ -72,11 +82,17 @@ void set_tuned(blip_table_s* t, int mode, int64_t npos, int P, int OE);
 // Launch the tiled (or FP64-accumulate) kernel.  perm/dev_count select the
 // sorted persistent form used for batches; grid is then the workgroup count.
 int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
-                 void* lap, int kind, int P, int OE, const int* perm, const int64_t* dev_count,
-                 int* xcd_next, int grid, bool chunk_major, hipStream_t s);
+                 void* lap, int kind, int P, int OE, const int* perm, const double* spos,
+                 const int64_t* dev_count, int* xcd_next, int grid, bool chunk_major,
+                 hipStream_t s, const RatioArgs* ratio = nullptr);
 bool valid_oe(const blip_table_s* t, int OE);
 int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
                     void* lap);
+int check_ratio_args(blip_table t, int64_t npos, const double* pos, const double* inv_rows,
+                     int64_t inv_ld, const int64_t* row_of, double* ratio, double* grad_ratio,
+                     double* lap_ratio);
+// P and o for the ratio epilogue (P <= 16, at most 16 orbital chunks).
+int ratio_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE);
 void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t grid, Cfg& c,
               KArgs& a);
 int upload_table(blip_table_s* t, const void* host);

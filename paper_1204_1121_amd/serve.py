@@ -2,7 +2,7 @@
 
 Requests come from many Monte Carlo walkers of several resident systems
 (each system is one coefficient table kept on the GPU).  A request is one
-walker's quasi-simultaneous move block (Sec. III.A): k positions whose
+walker's quasi-simultaneous move block (Sec. IV.A): k positions whose
 orbitals, gradients and Laplacians are wanted.  Because every moved electron
 is an independent evaluation against its system's table (Eq. (11.12.23.1)),
 requests of the same system can be packed into one batched launch and

@@ -98,3 +98,41 @@ def test_eval_rejects_bad_handle(blip):
 
 def test_version_string(blip):
     assert "gfx950" in blip.version()
+
+
+def test_sm_update_argument_errors(blip):
+    """blip_sm_update validates sizes, indices, alignment and the workspace
+    on the host; none of these calls reaches the device (fake pointers)."""
+    L = blip.lib()
+    n = 64
+    ws = L.blip_sm_workspace_size(n)
+    assert ws == 4 * 32 * n * 8
+    assert L.blip_sm_workspace_size(0) == 0 and L.blip_sm_workspace_size(4097) == 0
+    dev = ctypes.c_void_p(0x10000)          # never dereferenced: every call below fails first
+    cols = np.array([3, 70], dtype=np.int64)
+    cp = cols.ctypes.data_as(ctypes.c_void_p)
+
+    def call(n=n, inv=dev, ld=n, u=dev, u_nrows=n, u_ld=n, c=cp, urow=None, k=2,
+             ratios=dev, w=dev, wb=ws):
+        return L.blip_sm_update(n, inv, ld, u, u_nrows, u_ld, c, urow, k, ratios, w, wb, None)
+
+    assert call() == -1 and "cols[1]" in L.blip_last_error().decode()
+    ok = np.array([3, 5], dtype=np.int64)
+    okp = ok.ctypes.data_as(ctypes.c_void_p)
+    assert call(n=0, c=okp) == -1
+    assert call(n=4097, ld=4097, u_ld=4097, c=okp) == -1
+    assert call(ld=n - 1, c=okp) == -1
+    assert call(u_ld=n - 1, c=okp) == -1
+    assert call(k=-1, c=okp) == -1
+    assert call(c=None) == -1
+    assert call(inv=None, c=okp) == -1
+    assert call(u_nrows=5, c=okp) == -1 and "row 5" in L.blip_last_error().decode()
+    bad_row = np.array([0, -1], dtype=np.int64)
+    assert call(c=okp, urow=bad_row.ctypes.data_as(ctypes.c_void_p)) == -1
+    assert call(c=okp, w=None) == -1
+    assert call(c=okp, wb=ws - 1) == -1
+    assert call(c=okp, inv=ctypes.c_void_p(0x10004)) == -5
+    assert call(c=okp, u=ctypes.c_void_p(0x10002)) == -5
+    assert call(c=okp, ratios=ctypes.c_void_p(0x10004)) == -5
+    assert call(c=okp, w=ctypes.c_void_p(0x10004)) == -5
+    assert call(c=None, k=0, w=None, wb=0) == 0          # k = 0: nothing to do

@@ -1,0 +1,153 @@
+"""Fused acceptance ratios (blip_eval_ratio) against the oracle's ratio, and
+against an FP64 dot of blip_eval's own FP32 orbitals with the inverse."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1204_1121_amd import workloads as wl
+from tests.gpu_util import say, to_np
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[5.0, 0.3, 0.1], [0.2, 4.5, 0.4], [0.1, -0.3, 6.0]])
+
+
+@pytest.fixture(scope="module")
+def blip():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    from paper_1204_1121_amd import blip as b
+    b.lib()
+    return b
+
+
+def setup(A, n, c, nel, seed, sigma=0.4):
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(0, 1, (nel, 3)) @ A
+    D = oracle.evaluate(A, n, c, R, want=("val",), nthreads=8)["val"]
+    Dinv = np.linalg.inv(D)
+    moves = R + rng.normal(0, sigma, R.shape)
+    return R, Dinv.T.copy(), moves
+
+
+def check_ratio(got, ref, vals, inv_rows, rows, tol, label):
+    """|y - y*| <= tol * sum_l |y_l| |Dinv[l, c]| per position (the sum's
+    own scale), for ratio, gradient and Laplacian."""
+    w = np.abs(inv_rows[rows])
+    for key, part in (("ratio", "val"), ("grad", "grad"), ("lap", "lap")):
+        if got.get(key) is None:
+            continue
+        if key == "grad":
+            scale = np.einsum("jcl,jl->jc", np.abs(vals[part]), w)
+        else:
+            scale = np.einsum("jl,jl->j", np.abs(vals[part]), w)
+        err = np.max(np.abs(got[key] - ref[key]) / scale)
+        say(f"  {label} {key}: max error / scale = {err:.2e}")
+        assert err <= tol, (label, key, err)
+
+
+def test_small_skewed_ratio(blip):
+    rng = np.random.default_rng(3)
+    n = (9, 10, 11)
+    L = 37
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    R, inv_rows, moves = setup(SKEW, n, c, L, 1)
+    t = blip.Table(SKEW, n, c, "f32")
+    say("ratio: skewed cell, L=37")
+    ref = oracle.ratio(SKEW, n, c, moves, inv_rows, np.arange(L), nthreads=4)
+    vals = oracle.evaluate(SKEW, n, c, moves, nthreads=4)
+    p = torch.from_numpy(moves).cuda()
+    inv = torch.from_numpy(inv_rows).cuda()
+    r, g, l = t.ratio(p, inv)
+    torch.cuda.synchronize()
+    got = {"ratio": to_np(r), "grad": to_np(g), "lap": to_np(l)}
+    check_ratio(got, ref, vals, inv_rows, np.arange(L), 1e-5, "vs oracle")
+    # the epilogue itself: FP64 dot of the kernel's own FP32 orbitals
+    v, gg, ll = t.eval(p)
+    torch.cuda.synchronize()
+    mine = {"ratio": np.einsum("jl,jl->j", to_np(v).astype(np.float64), inv_rows),
+            "grad": np.einsum("jcl,jl->jc", to_np(gg).astype(np.float64), inv_rows),
+            "lap": np.einsum("jl,jl->j", to_np(ll).astype(np.float64), inv_rows)}
+    check_ratio(got, mine, vals, inv_rows, np.arange(L), 1e-13, "vs dot of blip_eval")
+    # values-only kernel and a row map (reversed electrons)
+    r2, g2, l2 = t.ratio(p, inv, grad=False)
+    torch.cuda.synchronize()
+    assert g2 is None and torch.equal(r2, r)
+    rows = torch.arange(L - 1, -1, -1, dtype=torch.int64, device="cuda")
+    r3, _, _ = t.ratio(p, inv, row_of=rows)
+    torch.cuda.synchronize()
+    ref3 = oracle.ratio(SKEW, n, c, moves, inv_rows, np.arange(L - 1, -1, -1))
+    check_ratio({"ratio": to_np(r3)}, ref3, vals, inv_rows, np.arange(L - 1, -1, -1), 1e-5,
+                "row map")
+    t.free()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_tio2_one_spin_ratios(blip, storage):
+    """768 electrons of one spin on the 768-orbital table: D from the old
+    configuration, its inverse, and a quasi-simultaneous move of every
+    electron."""
+    spec = wl.spec_tio2()
+    say(f"ratio: 72x72x48 x 768 table, 768 moves, {storage}")
+    c = wl.coefficients(spec)
+    R, inv_rows, moves = setup(spec.lattice, spec.n, c, 768, 7)
+    t = blip.Table(spec.lattice, spec.n, c, storage)
+    p = torch.from_numpy(moves).cuda()
+    r, g, l = t.ratio(p, torch.from_numpy(inv_rows).cuda())
+    torch.cuda.synchronize()
+    got = {"ratio": to_np(r), "grad": to_np(g), "lap": to_np(l)}
+    ref = oracle.ratio(spec.lattice, spec.n, c, moves, inv_rows, np.arange(768), nthreads=8)
+    vals = oracle.evaluate(spec.lattice, spec.n, c, moves, nthreads=8)
+    check_ratio(got, ref, vals, inv_rows, np.arange(768), 1e-5 if storage == "f32" else 1e-2,
+                storage)
+    t.free()
+
+
+def test_complex_table_rejected(blip):
+    c = np.zeros((4, 4, 4, 2), dtype=np.complex64)
+    t = blip.Table(np.eye(3) * 4.0, (4, 4, 4), c, "c64")
+    p = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    inv = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(blip.BlipError) as ei:
+        t.ratio(p, inv)
+    assert ei.value.status == -4
+    t.free()
+
+
+def test_batched_ratio_equals_per_walker(blip):
+    """Walkers with their own inverses and ragged move blocks in one sorted
+    persistent launch: equal bit for bit to blip_eval_ratio per walker."""
+    rng = np.random.default_rng(11)
+    n = (12, 11, 10)
+    L = 37
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    t = blip.Table(SKEW, n, c, "f32")
+    nwalk = 8
+    invs, blocks, rows = [], [], []
+    for w in range(nwalk):
+        R, inv_rows, moves = setup(SKEW, n, c, L, 100 + w)
+        k = int(rng.integers(1, L + 1))
+        who = rng.choice(L, k, replace=False)          # electrons this walker moves
+        invs.append(inv_rows)
+        blocks.append(moves[who])
+        rows.append(w * L + who)
+    pos = np.concatenate(blocks)
+    off = np.zeros(nwalk + 1, dtype=np.int64)
+    off[1:] = np.cumsum([b.shape[0] for b in blocks])
+    allinv = torch.from_numpy(np.concatenate(invs)).cuda()
+    row_of = torch.from_numpy(np.concatenate(rows).astype(np.int64)).cuda()
+    p = torch.from_numpy(pos).cuda()
+    say(f"batched ratio: {nwalk} walkers, {pos.shape[0]} moves")
+    rb, gb, lb = t.ratio_batched(p, torch.from_numpy(off).cuda(), allinv, row_of=row_of)
+    torch.cuda.synchronize()
+    for w in range(nwalk):
+        a, b = int(off[w]), int(off[w + 1])
+        r, g, l = t.ratio(p[a:b].contiguous(), allinv, row_of=row_of[a:b].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(rb[a:b], r) and torch.equal(gb[a:b], g) and torch.equal(lb[a:b], l)
+    ref = oracle.ratio(SKEW, n, c, pos, np.concatenate(invs), np.concatenate(rows))
+    vals = oracle.evaluate(SKEW, n, c, pos)
+    check_ratio({"ratio": to_np(rb), "grad": to_np(gb), "lap": to_np(lb)}, ref, vals,
+                np.concatenate(invs), np.concatenate(rows), 1e-5, "batched vs oracle")
+    t.free()

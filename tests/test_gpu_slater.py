@@ -1,0 +1,183 @@
+"""Sherman-Morrison update of the inverse Slater matrix on the GPU
+(blip_sm_update) against the oracle's sequential rank-1 updates (Sec. VI.D).
+
+Both sides compute in FP64 from the same FP32 orbital rows; they differ only
+in the order of rounding (one rank-k correction per 32 moves against k
+rank-1 corrections).  The bar for B after the moves is
+
+    |B_gpu - B_oracle| <= 64 * n * eps * cond(D_new) * max|B_oracle|,
+
+first-order perturbation of a matrix inverse with O(n) rounding per entry,
+and for each sequential ratio the same bound relative to the ratio (the
+2-norm condition number from power iterations on D_new and the oracle's
+inverse, with a factor 2 to stay above the true value)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import slater
+from tests.gpu_util import say, to_np
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def blip():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    from paper_1204_1121_amd import blip as b
+    b.lib()
+    return b
+
+
+def case(seed, n, k, repeats=False):
+    """Well-conditioned D (electron rows), the transposed inverse, and k
+    accepted moves: new rows near the old ones, rounded to FP32 (as
+    blip_eval writes them), stored one per electron in a [n, n] matrix."""
+    rng = np.random.default_rng(seed)
+    D = 2.0 * np.eye(n) + rng.normal(0, 1.0 / np.sqrt(n), (n, n))
+    inv_t = np.linalg.inv(D).T.copy()
+    if repeats:
+        cols = rng.integers(0, n, k)
+    else:
+        cols = rng.permutation(n)[:k]
+    U = (D + rng.normal(0, 0.3, (n, n))).astype(np.float32)
+    return D, inv_t, cols.astype(np.int64), U
+
+
+def norm2(M, iters=40):
+    """2-norm by power iteration on M^T M, times 2: power iteration
+    approaches the norm from below, and the margin keeps the bound an upper
+    one (O(n^2) per step, so no factorisation at n = 4096)."""
+    x = np.random.default_rng(0).normal(size=M.shape[1])
+    for _ in range(iters):
+        x = M.T @ (M @ x)
+        x /= np.linalg.norm(x)
+    return 2.0 * np.linalg.norm(M @ x)
+
+
+def final_matrix(D, cols, rows):
+    D = D.copy()
+    for c, r in zip(cols, rows):
+        D[c] = r
+    return D
+
+
+def check(blip, D, inv_t, cols, U, u_row=None, label=""):
+    n = D.shape[0]
+    urow = cols if u_row is None else np.asarray(u_row)
+    rows = U[urow].astype(np.float64)
+    want_b, want_r = slater.sm_update(inv_t, rows, cols)
+    inv = torch.from_numpy(inv_t).cuda()
+    u = torch.from_numpy(U).cuda()
+    r = blip.sm_update(inv, u, cols, u_row=u_row)
+    torch.cuda.synchronize()
+    got_b, got_r = to_np(inv), to_np(r)
+    cond = norm2(final_matrix(D, cols, rows)) * norm2(want_b)
+    tol = 64 * n * EPS * cond
+    eb = np.abs(got_b - want_b).max() / np.abs(want_b).max()
+    er = np.max(np.abs(got_r - want_r) / np.abs(want_r)) if len(cols) else 0.0
+    say(f"{label} n={n} k={len(cols)} cond={cond:.1e}: B err {eb:.1e}, ratio err {er:.1e} "
+        f"(bar {tol:.1e})")
+    assert eb <= tol and er <= tol
+    return got_b, got_r
+
+
+def test_small_several_chunks_ragged(blip):
+    """n = 101 (ragged last row tile), 70 moves: chunks of 32, 32 and 6."""
+    check(blip, *case(0, 101, 70), label="chunks")
+
+
+def test_repeated_electrons(blip):
+    """Electrons moved more than once in one call: chunks split at repeats;
+    u_row gives each move its own new row."""
+    D, inv_t, cols, U = case(1, 64, 90, repeats=True)
+    assert len(set(cols.tolist())) < len(cols)
+    rng = np.random.default_rng(11)
+    Ubig = np.concatenate([U, (D + rng.normal(0, 0.3, D.shape)).astype(np.float32)])
+    u_row = np.where(rng.random(len(cols)) < 0.5, cols, cols + 64)
+    check(blip, D, inv_t, cols, Ubig, u_row=u_row, label="repeats")
+
+
+def test_one_move_and_no_moves(blip):
+    D, inv_t, cols, U = case(2, 40, 1)
+    check(blip, D, inv_t, cols, U, label="one move")
+    inv = torch.from_numpy(inv_t).cuda()
+    r = blip.sm_update(inv, torch.from_numpy(U).cuda(), [])
+    torch.cuda.synchronize()
+    assert r.numel() == 0
+    np.testing.assert_array_equal(to_np(inv), inv_t)
+
+
+def test_unmoved_electrons_leave_inverse(blip):
+    """Moves that give electrons their own rows back: every ratio 1, B kept."""
+    rng = np.random.default_rng(3)
+    n = 96
+    D = (2.0 * np.eye(n) + rng.normal(0, 0.1, (n, n))).astype(np.float32).astype(np.float64)
+    inv_t = np.linalg.inv(D).T.copy()
+    cols = rng.permutation(n)[:50].astype(np.int64)
+    inv = torch.from_numpy(inv_t).cuda()
+    r = blip.sm_update(inv, torch.from_numpy(D.astype(np.float32)).cuda(), cols)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(to_np(r), 1.0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(to_np(inv), inv_t, rtol=0, atol=1e-12 * np.abs(inv_t).max())
+
+
+@pytest.mark.parametrize("n", [1, 2, 33, 1024, 1025, 2049, 4096])
+def test_orders_and_row_tilings(blip, n):
+    """Every rows-per-workgroup variant (4 up to n = 1024, 2 up to 2048, 1
+    above), the smallest orders and the largest accepted one."""
+    k = min(n, 40)
+    check(blip, *case(100 + n, n, k), label="order")
+
+
+def test_padded_leading_dimensions(blip):
+    """inv and u with row strides above n (views into wider buffers)."""
+    D, inv_t, cols, U = case(4, 70, 45)
+    wide = np.full((70, 80), 7.0)
+    wide[:, :70] = inv_t
+    base = torch.from_numpy(wide).cuda()
+    inv = base[:, :70]
+    Uw = np.full((70, 75), 3.0, dtype=np.float32)
+    Uw[:, :70] = U
+    u = torch.from_numpy(Uw).cuda()[:, :70]
+    want_b, want_r = slater.sm_update(inv_t, U[cols].astype(np.float64), cols)
+    r = blip.sm_update(inv, u, cols)
+    torch.cuda.synchronize()
+    full = base.cpu().numpy()
+    assert np.all(full[:, 70:] == 7.0), "columns past n were written"
+    np.testing.assert_allclose(full[:, :70], want_b, rtol=0, atol=1e-10 * np.abs(want_b).max())
+    np.testing.assert_allclose(to_np(r), want_r, rtol=1e-10)
+
+
+def test_quasi_simultaneous_step_tio2(blip):
+    """One spin of the TiO2 block (768 electrons, 768 orbitals of the
+    72x72x48 table): the Slater matrix from blip_eval at the old positions,
+    trial moves, acceptance from blip_eval_ratio against the old inverse,
+    then the inverse updated for the accepted moves.  The first accepted
+    move's sequential ratio is its quasi-simultaneous ratio."""
+    from paper_1204_1121_amd import workloads as wl
+    spec = wl.spec_tio2()
+    c = wl.coefficients(spec)
+    t = blip.Table(spec.lattice, spec.n, c, "f32")
+    del c
+    rng = np.random.default_rng(5)
+    n = spec.norb
+    old = rng.uniform(0, 1, (n, 3)) @ spec.lattice
+    new = old + rng.normal(0, 0.35, old.shape)
+    val_old = to_np(t.eval(torch.from_numpy(old).cuda(), grad=False)[0]).astype(np.float64)
+    inv_t = np.linalg.inv(val_old).T.copy()
+    newd = torch.from_numpy(new).cuda()
+    U = t.eval(newd, grad=False)[0]
+    inv = torch.from_numpy(inv_t).cuda()
+    q, _, _ = t.ratio(newd, inv, grad=False)
+    qs = to_np(q)
+    accept = rng.random(n) < np.minimum(1.0, qs ** 2)
+    cols = np.nonzero(accept)[0].astype(np.int64)
+    say(f"TiO2 Q.S. step: {len(cols)} of {n} moves accepted")
+    assert 0 < len(cols) < n
+    got_b, got_r = check(blip, val_old, inv_t, cols, to_np(U), label="TiO2")
+    assert got_r[0] == pytest.approx(qs[cols[0]], rel=1e-10)
+    t.free()
