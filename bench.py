@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "orbital evals/s (val+grad+lap, 768 orbs) & HBM GB/s vs plain; p50/p99 served"
 UNIT = "orbital evals/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (and matrix) peak
 NROT = 16
 COUNTERS = os.path.join(ROOT, "profiles", "tiled_kernel_tio2_block1536_counters.json")
 KERNEL_SOURCES = ["paper_1204_1121_amd/csrc/blip_device.hpp",
@@ -134,6 +135,57 @@ def cpu_baseline(spec, coef, npos, budget_s=12.0):
             "kind": "oracle",
             "sample": f"{nblk} move blocks of {npos} positions ({sample.shape[0]} positions "
                       f"x {L} orbitals, val+grad+lap, FP64): {dt:.1f} s on {threads} threads"}
+
+
+def bench_sm(args, with_cpu):
+    """Sherman-Morrison update of one spin's inverse after a quasi-simultaneous
+    step: n = 768 electrons (one spin of the TiO2 block), K = 384 accepted
+    moves (half), in electron order.  Synthetic matrix D = 2I + N(0, 1/n)
+    and new rows D + N(0, 0.3^2) as FP32; the kernel does the same arithmetic
+    whatever the values.  Every step re-applies the same moves to the updated
+    inverse (ratios 1 from the second step on)."""
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    n, K = 768, 384
+    rng = np.random.default_rng(wl.SEED_BASE + 7)
+    D = 2.0 * np.eye(n) + rng.normal(0, 1.0 / np.sqrt(n), (n, n))
+    inv_t = np.linalg.inv(D).T.copy()
+    U = (D + rng.normal(0, 0.3, (n, n))).astype(np.float32)
+    cols = np.sort(rng.permutation(n)[:K]).astype(np.int64)
+    inv = torch.from_numpy(inv_t).cuda()
+    u = torch.from_numpy(U).cuda()
+    ws = blip.sm_workspace(n)
+    ratios = torch.empty(K, dtype=torch.float64, device="cuda")
+
+    def step(_):
+        blip.sm_update(inv, u, cols, ratios=ratios, workspace=ws, stream=stream)
+    steps = max(20, min(args.steps, 200))
+    wall, t = time_region(step, [None], steps, 5, stream)
+    launches = (K + 31) // 32 + 1
+    flop = 4.0 * n * n * K                      # 2 n^2 FMA per move
+    res = {"n": n, "accepted_moves": K, "launches_per_step": launches,
+           "us_per_step": t * 1e6, "wall_us_per_step": wall / steps * 1e6,
+           "moves_per_s": K / t,
+           "roofline": {"bound": "alu", "achieved": flop / t / 1e12, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flop / t / 1e12 / FP64_PEAK_TFLOPS},
+           "b_passes": {"blocked": launches, "rank1_per_move": 2 * K},
+           "inputs": "D = 2I + N(0,1/n), new rows D + N(0,0.09) in FP32, 384 of 768 moved"}
+    if with_cpu:
+        from oracle import slater
+        t0 = time.perf_counter()
+        slater.sm_update(inv_t, U[cols].astype(np.float64), cols)
+        dt = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            cores = 1
+        res["cpu_baseline"] = {"value": K / dt, "unit": "moves/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"one step of {K} moves at n = {n}: {dt:.2f} s"}
+    return res
 
 
 def bench_batched(table, spec, args, nbatch=4):
@@ -352,6 +404,8 @@ def main():
                     help="write the shapes chosen by this run to this JSON file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-ratio", action="store_true", help="skip the fused-ratio figure")
+    ap.add_argument("--no-sm", action="store_true",
+                    help="skip the Sherman-Morrison update figure")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the storage-dtype / complex k-point section")
     ap.add_argument("--serve-requests", type=int, default=10000,
@@ -485,6 +539,13 @@ def main():
                            "outputs": "ratio + grad ratio + lap ratio per position (FP64)"}
         log(f"ratio: {tr * 1e6:.1f} us per block (ratio, grad, lap) vs {t_kernel * 1e6:.1f} us "
             f"for the orbitals")
+
+    if not args.no_sm:
+        result["sm_update"] = bench_sm(args, not args.no_cpu_baseline)
+        sm = result["sm_update"]
+        log(f"sm_update: {sm['us_per_step']:.1f} us per step of {sm['accepted_moves']} moves at "
+            f"n = {sm['n']} ({sm['launches_per_step']} launches), "
+            f"{sm['roofline']['achieved']:.2f} TFLOP/s FP64")
 
     if not args.no_cold:
         # Cold Infinity Cache: read 1 GiB of unrelated data before every

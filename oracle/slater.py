@@ -33,7 +33,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def sm_update(inv_t, u, cols):
+def sm_update(inv_t, u, cols, return_rows: bool = False):
     """Apply accepted moves one after another with Sherman-Morrison.
 
     inv_t  [N, N] transposed inverse before the moves (not modified).
@@ -43,7 +43,9 @@ def sm_update(inv_t, u, cols):
 
     Returns (inv_t after all moves, ratios[k]), where ratios[m] is
     det(D^(m)) / det(D^(m-1)) for the matrix after m moves: the ratio of move
-    m against the configuration that already holds moves 0..m-1.
+    m against the configuration that already holds moves 0..m-1.  With
+    return_rows, also the row cols[m] of inv_t just before move m ([k, N]),
+    the row that move m's ratio is the dot product with.
     """
     b = np.array(inv_t, dtype=np.float64, copy=True)
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
@@ -52,14 +54,17 @@ def sm_update(inv_t, u, cols):
     if b.shape != (n, n) or u.shape != (cols.shape[0], n):
         raise ValueError("inv_t must be N x N and u k x N")
     ratios = np.empty(cols.shape[0], dtype=np.float64)
+    before = np.empty((cols.shape[0], n)) if return_rows else None
     for m, c in enumerate(cols):
         v = b @ u[m]                   # ddot of the new row with every column
         r = v[c]
         ratios[m] = r
         old_c = b[c].copy()
+        if return_rows:
+            before[m] = old_c
         for i in range(n):             # daxpy per column of the inverse
             if i == c:
                 b[i] = old_c / r
             else:
                 b[i] = b[i] - (v[i] / r) * old_c
-    return b, ratios
+    return (b, ratios, before) if return_rows else (b, ratios)

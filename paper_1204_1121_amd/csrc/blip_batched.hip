@@ -51,21 +51,57 @@ __global__ void fill_int_kernel(int* p, int n, int v)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Wave-aggregated counter increment: the active lanes of a wavefront are
+// grouped by key (a ballot per distinct key, no memory traffic in the loop),
+// then one lane per group adds the group's size with a single atomic and the
+// others take their slot from it.  Positions that crowd into a few bins then
+// cost one atomic per bin per wavefront instead of one per position.  Must be
+// called by every lane of the wavefront; returns old counter + rank in group.
+__device__ __forceinline__ int wave_aggregated_add(int* counters, int key, bool active)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int leader = lane, rank = 0, size = 0;
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int l = __ffsll((unsigned long long)pending) - 1;
+        const int lkey = __shfl(key, l, 64);
+        const uint64_t same = __ballot(active && key == lkey);
+        if (active && key == lkey) {
+            leader = l;
+            rank = __popcll(same & below);
+        }
+        if (lane == l) size = __popcll(same);
+        pending &= ~same;
+    }
+    int base = 0;
+    if (active && lane == leader) base = atomicAdd(&counters[key], size);
+    base = __shfl(base, leader, 64);
+    return base + rank;
+}
+
+// The grid-stride loops below step whole workgroups at a time so every lane
+// of a wavefront reaches wave_aggregated_add together.
 __global__ void bin_kernel(const KArgs a, SortArgs s)
 {
     const int64_t n = batch_count(a);
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const double* rp = a.pos + 3 * j;
-        double r[3] = {rp[0], rp[1], rp[2]};
-        bool bad = false;
-        int i0[3];
-        double f[3];
-        wrap_split(a, r, i0, f, bad);
-        const int bx = i0[0] >> s.bshift, by = i0[1] >> s.bshift, bz = i0[2] >> s.bshift;
-        const int key = s.rank[(bx * s.nb1 + by) * s.nb2 + bz];
-        s.keys[j] = key;
-        atomicAdd(&s.counts[key], 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t jb = (int64_t)blockIdx.x * blockDim.x; jb < n; jb += stride) {
+        const int64_t j = jb + threadIdx.x;
+        const bool active = j < n;
+        int key = -1;
+        if (active) {
+            const double* rp = a.pos + 3 * j;
+            double r[3] = {rp[0], rp[1], rp[2]};
+            bool bad = false;
+            int i0[3];
+            double f[3];
+            wrap_split(a, r, i0, f, bad);
+            const int bx = i0[0] >> s.bshift, by = i0[1] >> s.bshift, bz = i0[2] >> s.bshift;
+            key = s.rank[(bx * s.nb1 + by) * s.nb2 + bz];
+            s.keys[j] = key;
+        }
+        (void)wave_aggregated_add(s.counts, key, active);
     }
 }
 
@@ -116,13 +152,18 @@ __global__ void __launch_bounds__(1024) scan_kernel(SortArgs s)
 __global__ void scatter_kernel(const KArgs a, SortArgs s)
 {
     const int64_t n = batch_count(a);
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int slot = atomicAdd(&s.cursor[s.keys[j]], 1);
-        s.perm[slot] = (int)j;
-        s.spos[3 * (int64_t)slot] = a.pos[3 * j];
-        s.spos[3 * (int64_t)slot + 1] = a.pos[3 * j + 1];
-        s.spos[3 * (int64_t)slot + 2] = a.pos[3 * j + 2];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t jb = (int64_t)blockIdx.x * blockDim.x; jb < n; jb += stride) {
+        const int64_t j = jb + threadIdx.x;
+        const bool active = j < n;
+        const int key = active ? s.keys[j] : -1;
+        const int slot = wave_aggregated_add(s.cursor, key, active);
+        if (active) {
+            s.perm[slot] = (int)j;
+            s.spos[3 * (int64_t)slot] = a.pos[3 * j];
+            s.spos[3 * (int64_t)slot + 1] = a.pos[3 * j + 1];
+            s.spos[3 * (int64_t)slot + 2] = a.pos[3 * j + 2];
+        }
     }
 }
 

@@ -18,8 +18,10 @@
 // sequential dependence.  Its m-th pivot is the ratio of move m against the
 // configuration that already holds moves 0..m-1, and the product of the
 // pivots is det(D')/det(D).  Each launch also forms V and R of the next
-// chunk from the rows it has just updated.  So a step of K accepted moves
-// takes ceil(K/32)+1 launches, and each launch reads and writes B once.
+// chunk from the rows it has just updated; V is left as one partial sum per
+// column tile, which the next launch adds in a fixed order.  So a step of K
+// accepted moves takes ceil(K/32)+1 launches, and each launch reads and
+// writes B once.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -31,196 +33,279 @@
 namespace blip {
 namespace {
 
-constexpr int kSmChunk = 32;                       // moves applied per launch
-constexpr int kSmThreads = 256;                    // four waves
-constexpr int kSmTile = 64;                        // columns of U staged per pass
-constexpr int kSmSplits = kSmThreads / kSmChunk;   // column splits in the V pass
-constexpr int kSmPad = kSmChunk + 1;               // LDS row pitch (bank spread)
+constexpr int kSmChunk = 32;        // moves applied per launch
+constexpr int kSmThreads = 256;     // four waves
+constexpr int kSmRows = 8;          // rows of B per workgroup
+constexpr int kSmPiece = 128;       // columns per pass inside a column tile
+constexpr int kSmPad = kSmChunk + 1;
 constexpr int64_t kSmMaxN = 4096;
+constexpr int kSmMaxTiles = 4;      // column tiles (partial sums of V per row)
 
 struct SmArgs {
     int n;
     int kp;              // moves of the chunk applied by this launch (0: none)
     int kn;              // moves of the chunk prepared for the next (0: none)
+    int tl;              // columns per column tile (a multiple of kSmPiece)
+    int nct;             // column tiles
     double* inv;         // B, row i at inv + i * ld
     int64_t ld;
     const float* u;      // new orbital rows, row r at u + r * u_ld
     int64_t u_ld;
-    const double* Vp;    // [n][kSmChunk] of the applied chunk
-    const double* Rp;    // [kSmChunk][n]
+    const double* Pp;    // V of the applied chunk as column-tile partials [nct][n][32]
+    const double* Rp;    // [32][n]: its moved rows of B
     double* ratio;       // kp sequential ratios, or null
-    double* Vn;          // [n][kSmChunk] of the next chunk
-    double* Rn;          // [kSmChunk][n]
+    double* Pn;          // partials of V of the next chunk [nct][n][32]
+    double* Rn;          // [32][n]
     int colp[kSmChunk];  // electrons of the applied chunk, in move order
     int coln[kSmChunk];  // electrons of the next chunk
     int urow[kSmChunk];  // rows of u holding the next chunk's new orbitals
 };
 
-// Dynamic LDS layout in bytes for T rows per workgroup and n columns.
-struct SmLds {
-    size_t g, y, piv, ut, arow, total;
+// Column tiles: at most kSmMaxTiles per row (so summing V's partials stays
+// cheap), each a multiple of kSmPiece wide.
+struct SmShape {
+    int tl, nct;
 };
 
-__host__ __device__ inline SmLds sm_lds(int T, int n)
+inline SmShape sm_shape(int64_t n)
 {
-    SmLds s;
-    s.g = 0;   // double [2][kSmChunk][kSmPad]; later the split sums of V
-    s.y = s.g + 2 * kSmChunk * kSmPad * sizeof(double);
-    s.piv = s.y + (size_t)T * kSmChunk * sizeof(double);
-    s.ut = s.piv + kSmChunk * sizeof(double);   // float [kSmTile][kSmPad]
-    s.arow = s.ut + ((kSmTile * kSmPad * sizeof(float) + 15) & ~size_t(15));
-    s.total = s.arow + (size_t)T * n * sizeof(double);   // double [T][n]
-    return s;
+    const int64_t want = (n + 255) / 256 < kSmMaxTiles ? (n + 255) / 256 : kSmMaxTiles;
+    const int64_t tl = ((n + want - 1) / want + kSmPiece - 1) / kSmPiece * kSmPiece;
+    return {(int)tl, (int)((n + tl - 1) / tl)};
 }
 
-inline int sm_rows(int64_t n) { return n <= 1024 ? 4 : (n <= 2048 ? 2 : 1); }
+// What a thread reads for one kSmPiece-wide pass: its column of B on its four
+// rows, the chunk's moved rows R at that column, and (for the next chunk) 16
+// new-orbital values at that column.  Loaded together so their latencies
+// overlap.
+struct SmFrag {
+    double b[4];
+    double r[kSmChunk];
+    float u[16];
+};
 
-// One launch: apply chunk p to rows [T*blockIdx.x, +T) of B, then form the
-// rows of V and R of chunk n from the updated rows.
-template <int T>
+// One launch: workgroup (x, y) applies chunk p to rows [8x, 8x+8) and
+// columns [y*tl, (y+1)*tl) of B, copies the moved rows of chunk n into Rn,
+// and writes its columns' share of V = B' U^T for chunk n to Pn[y].
+//
+// Loads are written without data-dependent branches: addresses are clamped
+// into bounds and unwanted values replaced by zero afterwards, so each group
+// of loads is issued back to back and waited for once.  Only the uniform
+// tests kp > 0 and kn > 0 guard buffers that may be absent.
 __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
 {
-    extern __shared__ __align__(16) unsigned char sm_raw[];
-    const SmLds lay = sm_lds(T, a.n);
-    double(*G)[kSmChunk][kSmPad] = reinterpret_cast<double(*)[kSmChunk][kSmPad]>(sm_raw + lay.g);
-    double* Y = reinterpret_cast<double*>(sm_raw + lay.y);         // [T][kSmChunk]
-    double* piv = reinterpret_cast<double*>(sm_raw + lay.piv);     // [kSmChunk]
-    float* Ut = reinterpret_cast<float*>(sm_raw + lay.ut);         // [kSmTile][kSmPad]
-    double* Arow = reinterpret_cast<double*>(sm_raw + lay.arow);   // [T][n]
-    double* red = reinterpret_cast<double*>(sm_raw + lay.g);       // [kSmSplits][T][kSmChunk]
-    __shared__ int slot[T];   // index of the row in the next chunk, or -1
+    __shared__ double bc[2][2][kSmChunk];       // pivot row / column, double-buffered
+    __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
+    __shared__ double Vl[kSmRows][kSmChunk];    // rows of V - E of this tile
+    __shared__ double Y[kSmRows][kSmChunk];     // rows of (V - E) S^{-1}
+    __shared__ double piv[kSmChunk];
+    __shared__ double Bt[kSmRows][kSmPiece];    // updated piece of B
+    __shared__ float Ut[kSmPiece][kSmPad];      // piece of U^T of the next chunk
+    __shared__ int lcolp[kSmChunk], lcoln[kSmChunk];
+    __shared__ int slot[kSmRows];               // row's index in the next chunk, or -1
 
     const int tid = threadIdx.x;
     const int n = a.n;
     const int kp = a.kp;
     const int kn = a.kn;
-    const int i0 = blockIdx.x * T;
+    const int nct = a.nct;
+    const int i0 = blockIdx.x * kSmRows;
+    const int c0 = blockIdx.y * a.tl;
+    const int cend = min(n, c0 + a.tl);
+    const int cc = tid % kSmPiece;                                  // column within a piece
+    const int h = __builtin_amdgcn_readfirstlane(tid / kSmPiece);   // rows 4h..4h+3 (per wave)
 
-    if (tid < T) {
-        int s = -1;
-        for (int m = 0; m < kn; ++m)
-            if (a.coln[m] == i0 + tid) s = m;
-        slot[tid] = s;
+    // index lists into LDS (uniform reads of the arguments, one select each)
+    if (tid < kSmChunk) {
+        int cp = 0, cn = 0;
+#pragma unroll
+        for (int m = 0; m < kSmChunk; ++m) {
+            cp = (tid == m) ? a.colp[m] : cp;
+            cn = (tid == m) ? a.coln[m] : cn;
+        }
+        lcolp[tid] = cp;
+        lcoln[tid] = cn;
     }
+
+    // A lane whose column is past the tile reads the tile's last column (in
+    // bounds) and its results are never stored; rows past n read row n-1.
+    // Zeroing uses only uniform conditions, so no load sits behind a branch.
+    auto fetch = [&](int q0, SmFrag& f) {
+        const int c = q0 + cc;
+        const int cl = c < cend ? c : cend - 1;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = i0 + 4 * h + rr;   // uniform per wave
+            f.b[rr] = a.inv[(int64_t)(i < n ? i : n - 1) * a.ld + cl];
+        }
+        if (kp > 0) {
+#pragma unroll
+            for (int m = 0; m < kSmChunk; ++m) f.r[m] = a.Rp[(int64_t)(m < kp ? m : kp - 1) * n + cl];
+        }
+        if (kn > 0) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int m = 16 * h + k;   // uniform per wave
+                f.u[k] = a.u[(int64_t)a.urow[m < kn ? m : kn - 1] * a.u_ld + cl];
+            }
+        }
+    };
+    SmFrag f;
+    fetch(c0, f);   // in flight while S is assembled and eliminated
     __syncthreads();
 
+    if (tid < kSmRows) {
+        int sl = -1;
+        for (int m = 0; m < kn; ++m)
+            if (lcoln[m] == i0 + tid) sl = m;
+        slot[tid] = sl;
+    }
+
     if (kp > 0) {
-        // S^{-1} by Gauss-Jordan without pivoting, ping-ponging between the
-        // two halves of G; unused rows and columns hold the identity.
-        for (int e = tid; e < kSmChunk * kSmChunk; e += kSmThreads) {
-            const int r = e / kSmChunk, c = e % kSmChunk;
-            G[0][r][c] = (r < kp && c < kp) ? a.Vp[(int64_t)a.colp[r] * kSmChunk + c]
-                                            : (r == c ? 1.0 : 0.0);
+        // S (rows of V on the moved rows) and this tile's rows of V - E, each
+        // the column-tile partials summed in order; unused rows and columns
+        // of S hold the identity.  Thread t owns S[t/32 + 8j][t%32], j < 4.
+        const int gc = tid % kSmChunk;
+        const int gr0 = tid / kSmChunk;
+        double part[4][kSmMaxTiles];
+        {
+            const int cq = gc < kp ? gc : kp - 1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = gr0 + 8 * j;
+                const int row = lcolp[r < kp ? r : kp - 1];
+#pragma unroll
+                for (int t = 0; t < kSmMaxTiles; ++t)
+                    part[j][t] = a.Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + cq];
+            }
         }
+        double vpart[kSmMaxTiles];
+        const int vr = tid / kSmChunk, vm = tid % kSmChunk;
+        const int vi = i0 + vr;
+        {
+            const int row = vi < n ? vi : n - 1;
+            const int mq = vm < kp ? vm : kp - 1;
+#pragma unroll
+            for (int t = 0; t < kSmMaxTiles; ++t)
+                vpart[t] = a.Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + mq];
+        }
+        double sv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = gr0 + 8 * j;
+            double v = 0.0;
+#pragma unroll
+            for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? part[j][t] : 0.0;
+            sv[j] = (r < kp && gc < kp) ? v : (r == gc ? 1.0 : 0.0);
+        }
+        {
+            double v = 0.0;
+#pragma unroll
+            for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? vpart[t] : 0.0;
+            if (lcolp[vm] == vi && vm < kp) v -= 1.0;
+            Vl[vr][vm] = (vi < n && vm < kp) ? v : 0.0;
+        }
+
+        // S^{-1} by Gauss-Jordan without pivoting, in registers: thread t
+        // keeps S[t/32 + 8j][t%32], j < 4.  Each step publishes pivot row p
+        // and column p through double-buffered LDS vectors (one barrier);
+        // every thread then reads what it needs in one round trip and
+        // updates its 4 entries.  The pivots are the sequential ratios.
         for (int p = 0; p < kp; ++p) {
+            const int b = p & 1;
+            const int jp = p >> 3;
+            if (gr0 == (p & 7)) bc[b][0][gc] = jp == 0 ? sv[0] : jp == 1 ? sv[1] : jp == 2 ? sv[2] : sv[3];
+            if (gc == p) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bc[b][1][gr0 + 8 * j] = sv[j];
+            }
             __syncthreads();
-            const double(*src)[kSmPad] = G[p & 1];
-            double(*dst)[kSmPad] = G[(p + 1) & 1];
-            const double d = src[p][p];
+            const double d = bc[b][0][p];
+            const double rowv = bc[b][0][gc];
+            double crp[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) crp[j] = bc[b][1][gr0 + 8 * j];
             const double rd = 1.0 / d;
-            for (int e = tid; e < kSmChunk * kSmChunk; e += kSmThreads) {
-                const int r = e / kSmChunk, c = e % kSmChunk;
-                double x;
-                if (r == p)
-                    x = (c == p) ? rd : src[p][c] * rd;
-                else if (c == p)
-                    x = -src[r][p] * rd;
-                else
-                    x = src[r][c] - src[r][p] * (src[p][c] * rd);
-                dst[r][c] = x;
+            // column p becomes -S[r][p]/d, row p becomes S[p][c]/d (1/d on
+            // the diagonal), the rest S[r][c] - S[r][p] S[p][c]/d
+            const bool pcol = (gc == p);
+            const double coef = pcol ? rd : rowv * rd;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double nv = fma(-crp[j], coef, pcol ? 0.0 : sv[j]);
+                sv[j] = (gr0 + 8 * j == p) ? coef : nv;
             }
             if (tid == 0) piv[p] = d;
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Sinv[gr0 + 8 * j][gc] = sv[j];
         __syncthreads();
-        const double(*Sinv)[kSmPad] = G[kp & 1];
-
-        // Y = (V - E) S^{-1} on this workgroup's rows
-        for (int e = tid; e < T * kSmChunk; e += kSmThreads) {
-            const int r = e / kSmChunk, m = e % kSmChunk;
-            const int i = i0 + r;
+        {
             double y = 0.0;
-            if (i < n && m < kp) {
-                for (int q = 0; q < kp; ++q) {
-                    const double v = a.Vp[(int64_t)i * kSmChunk + q] - (a.colp[q] == i ? 1.0 : 0.0);
-                    y = fma(v, Sinv[q][m], y);
-                }
-            }
-            Y[e] = y;
+            for (int q = 0; q < kp; ++q) y = fma(Vl[vr][q], Sinv[q][vm], y);
+            Y[vr][vm] = (vm < kp) ? y : 0.0;
         }
-        if (blockIdx.x == 0 && a.ratio != nullptr)
-            for (int m = tid; m < kp; m += kSmThreads) a.ratio[m] = piv[m];
-        __syncthreads();
+        if (blockIdx.x == 0 && blockIdx.y == 0 && a.ratio != nullptr && tid < kp) a.ratio[tid] = piv[tid];
     }
+    __syncthreads();
 
-    // B' = B - Y R on this workgroup's rows, one column per thread; the new
-    // rows stay in LDS for the V pass and the moved ones are copied to R.
-    for (int l = tid; l < n; l += kSmThreads) {
-        double acc[T];
+    // Pieces of kSmPiece columns: B' = B - Y R, the moved rows of the next
+    // chunk copied to Rn, then this piece's share of V = B' U^T.
+    const int vr = tid / kSmChunk, vm = tid % kSmChunk;   // V entry this thread sums
+    double vacc[4] = {0.0, 0.0, 0.0, 0.0};                 // four chains, added in order
+    for (int q0 = c0; q0 < cend; q0 += kSmPiece) {
+        const int c = q0 + cc;
+        double acc[4];
 #pragma unroll
-        for (int r = 0; r < T; ++r) acc[r] = (i0 + r < n) ? a.inv[(int64_t)(i0 + r) * a.ld + l] : 0.0;
-        for (int m = 0; m < kp; ++m) {
-            const double rv = a.Rp[(int64_t)m * n + l];
+        for (int rr = 0; rr < 4; ++rr) acc[rr] = f.b[rr];
+        if (kp > 0) {
+            // all 32 terms: Y is zero past kp and the rows of f.r past kp are
+            // clamped copies, so the loop has no branches and its LDS reads
+            // can all be in flight together
 #pragma unroll
-            for (int r = 0; r < T; ++r) acc[r] = fma(-Y[r * kSmChunk + m], rv, acc[r]);
+            for (int m = 0; m < kSmChunk; ++m) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[rr] = fma(-Y[4 * h + rr][m], f.r[m], acc[rr]);
+            }
         }
 #pragma unroll
-        for (int r = 0; r < T; ++r) {
+        for (int rr = 0; rr < 4; ++rr) {
+            const int r = 4 * h + rr;
             const int i = i0 + r;
-            if (i >= n) continue;
-            if (kp > 0) a.inv[(int64_t)i * a.ld + l] = acc[r];
-            if (kn > 0) {
-                Arow[r * n + l] = acc[r];
-                if (slot[r] >= 0) a.Rn[(int64_t)slot[r] * n + l] = acc[r];
+            if (c < cend && i < n) {
+                if (kp > 0) a.inv[(int64_t)i * a.ld + c] = acc[rr];
+                if (slot[r] >= 0) a.Rn[(int64_t)slot[r] * n + c] = acc[rr];
             }
         }
-    }
-    if (kn == 0) return;
-    __syncthreads();
-
-    // V of the next chunk: thread (split, m) sums B'[r][l] u_{c_m}[l] over the
-    // columns l = l0 + split + kSmSplits*j of each staged tile, for all T rows.
-    const int m = tid % kSmChunk;
-    const int split = tid / kSmChunk;
-    double acc[T];
+        if (kn > 0) {
 #pragma unroll
-    for (int r = 0; r < T; ++r) acc[r] = 0.0;
-    for (int l0 = 0; l0 < n; l0 += kSmTile) {
-        for (int e = tid; e < kSmChunk * kSmTile; e += kSmThreads) {
-            const int mm = e / kSmTile, j = e % kSmTile;
-            const int l = l0 + j;
-            Ut[j * kSmPad + mm] = (mm < kn && l < n) ? a.u[(int64_t)a.urow[mm] * a.u_ld + l] : 0.0f;
+            for (int rr = 0; rr < 4; ++rr) Bt[4 * h + rr][cc] = (c < cend && i0 + 4 * h + rr < n) ? acc[rr] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                Ut[cc][16 * h + k] = (c < cend && 16 * h + k < kn) ? f.u[k] : 0.0f;
         }
-        __syncthreads();
+        if (q0 + kSmPiece < cend) fetch(q0 + kSmPiece, f);   // next piece, in flight below
+        if (kn > 0) {
+            __syncthreads();
+#pragma unroll 4
+            for (int j = 0; j < kSmPiece; j += 4) {
 #pragma unroll
-        for (int jj = 0; jj < kSmTile / kSmSplits; ++jj) {
-            const int j = split + kSmSplits * jj;
-            const int l = l0 + j;
-            if (l < n) {
-                const double uv = (double)Ut[j * kSmPad + m];
-#pragma unroll
-                for (int r = 0; r < T; ++r) acc[r] = fma(Arow[r * n + l], uv, acc[r]);
+                for (int q = 0; q < 4; ++q) vacc[q] = fma(Bt[vr][j + q], (double)Ut[j + q][vm], vacc[q]);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < T; ++r) red[(split * T + r) * kSmChunk + m] = acc[r];
-    __syncthreads();
-    for (int e = tid; e < T * kSmChunk; e += kSmThreads) {
-        const int r = e / kSmChunk, mm = e % kSmChunk;
-        const int i = i0 + r;
-        if (i >= n || mm >= kn) continue;
-        double s = 0.0;
-        for (int q = 0; q < kSmSplits; ++q) s += red[(q * T + r) * kSmChunk + mm];
-        a.Vn[(int64_t)i * kSmChunk + mm] = s;
+    if (kn > 0) {
+        const int i = i0 + vr;
+        if (i < n && vm < kn)
+            a.Pn[((int64_t)blockIdx.y * n + i) * kSmChunk + vm] = (vacc[0] + vacc[1]) + (vacc[2] + vacc[3]);
     }
 }
 
-template <int T>
 hipError_t sm_launch(const SmArgs& a, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((a.n + T - 1) / T);
-    hipLaunchKernelGGL(sm_chunk_kernel<T>, dim3(grid), dim3(kSmThreads), sm_lds(T, a.n).total, s, a);
+    const dim3 grid((unsigned)((a.n + kSmRows - 1) / kSmRows), (unsigned)a.nct);
+    hipLaunchKernelGGL(sm_chunk_kernel, grid, dim3(kSmThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -236,7 +321,9 @@ extern "C" {
 BLIP_API size_t blip_sm_workspace_size(int64_t n)
 {
     if (n <= 0 || n > kSmMaxN) return 0;
-    return (size_t)4 * kSmChunk * (size_t)n * sizeof(double);
+    // two chunks in flight: V partials [nct][n][32] and R [32][n] for each
+    const SmShape sh = sm_shape(n);
+    return (size_t)2 * ((size_t)sh.nct + 1) * kSmChunk * (size_t)n * sizeof(double);
 }
 
 BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float* u,
@@ -283,15 +370,18 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
         ++len.back();
     }
 
+    const SmShape sh = sm_shape(n);
+    const size_t pv = (size_t)sh.nct * kSmChunk * n;   // doubles of one set of V partials
     double* ws = static_cast<double*>(workspace);
-    double* V[2] = {ws, ws + (size_t)kSmChunk * n};
-    double* R[2] = {ws + (size_t)2 * kSmChunk * n, ws + (size_t)3 * kSmChunk * n};
+    double* V[2] = {ws, ws + pv};
+    double* R[2] = {ws + 2 * pv, ws + 2 * pv + (size_t)kSmChunk * n};
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int T = sm_rows(n);
     const size_t nchunks = start.size();
     for (size_t c = 0; c <= nchunks; ++c) {
         SmArgs a{};
         a.n = (int)n;
+        a.tl = sh.tl;
+        a.nct = sh.nct;
         a.inv = inv;
         a.ld = inv_ld;
         a.u = u;
@@ -300,7 +390,7 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
             const size_t q = c - 1;
             a.kp = (int)len[q];
             for (int m = 0; m < a.kp; ++m) a.colp[m] = (int)cols[start[q] + m];
-            a.Vp = V[q & 1];
+            a.Pp = V[q & 1];
             a.Rp = R[q & 1];
             a.ratio = ratios ? ratios + start[q] : nullptr;
         }
@@ -310,10 +400,10 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
                 a.coln[m] = (int)cols[start[c] + m];
                 a.urow[m] = (int)(u_row ? u_row[start[c] + m] : cols[start[c] + m]);
             }
-            a.Vn = V[c & 1];
+            a.Pn = V[c & 1];
             a.Rn = R[c & 1];
         }
-        hipError_t e = T == 4 ? sm_launch<4>(a, s) : (T == 2 ? sm_launch<2>(a, s) : sm_launch<1>(a, s));
+        hipError_t e = sm_launch(a, s);
         if (e != hipSuccess) return fail_hip(e, "sm_chunk_kernel launch");
     }
     return BLIP_OK;

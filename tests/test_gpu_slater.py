@@ -8,7 +8,8 @@ rank-1 corrections).  The bar for B after the moves is
     |B_gpu - B_oracle| <= 64 * n * eps * cond(D_new) * max|B_oracle|,
 
 first-order perturbation of a matrix inverse with O(n) rounding per entry,
-and for each sequential ratio the same bound relative to the ratio (the
+and for each sequential ratio the same bound relative to the scale of its
+dot product, sum_l |u_l B[c][l]|, since a ratio can cancel (the
 2-norm condition number from power iterations on D_new and the oracle's
 inverse, with a factor 2 to stay above the true value)."""
 import numpy as np
@@ -69,7 +70,7 @@ def check(blip, D, inv_t, cols, U, u_row=None, label=""):
     n = D.shape[0]
     urow = cols if u_row is None else np.asarray(u_row)
     rows = U[urow].astype(np.float64)
-    want_b, want_r = slater.sm_update(inv_t, rows, cols)
+    want_b, want_r, before = slater.sm_update(inv_t, rows, cols, return_rows=True)
     inv = torch.from_numpy(inv_t).cuda()
     u = torch.from_numpy(U).cuda()
     r = blip.sm_update(inv, u, cols, u_row=u_row)
@@ -78,7 +79,10 @@ def check(blip, D, inv_t, cols, U, u_row=None, label=""):
     cond = norm2(final_matrix(D, cols, rows)) * norm2(want_b)
     tol = 64 * n * EPS * cond
     eb = np.abs(got_b - want_b).max() / np.abs(want_b).max()
-    er = np.max(np.abs(got_r - want_r) / np.abs(want_r)) if len(cols) else 0.0
+    # a ratio is a dot product that can cancel: its error is measured against
+    # the dot product's own scale, sum_l |u_l B[c][l]| (>= |ratio|)
+    scale = np.einsum("ml,ml->m", np.abs(rows), np.abs(before))
+    er = np.max(np.abs(got_r - want_r) / scale) if len(cols) else 0.0
     say(f"{label} n={n} k={len(cols)} cond={cond:.1e}: B err {eb:.1e}, ratio err {er:.1e} "
         f"(bar {tol:.1e})")
     assert eb <= tol and er <= tol
