@@ -243,8 +243,8 @@ static void eval_one(const double G[9], const double M[9], const double g[9],
         double cr = cos(kr), ci = sin(kr);
         for (l = 0; l < L; ++l) {
             double ur = val ? val[2 * l] : 0.0, ui = val ? val[2 * l + 1] : 0.0;
-            /* u is needed by grad and lap even when val is not requested;
-             * all three are requested together by the callers here. */
+            /* u (in val) is present whenever grad or lap is requested, and
+             * grad u whenever lap is: oracle_eval checks both */
             double gr[3], gi[3];
             if (grad) for (c = 0; c < 3; ++c) {
                 gr[c] = grad[2 * (c * L + l)];
@@ -284,8 +284,8 @@ static void eval_one(const double G[9], const double M[9], const double g[9],
  *   val      [npos][L], grad [npos][3][L], lap [npos][L] doubles (x2 when
  *            complex, interleaved); any of them may be NULL
  *   nthreads OpenMP threads over positions (<=0: all the runtime offers)
- * Returns 0, or -1 for bad arguments.  Needs pos and the work arrays when
- * a k-point is given: val, grad and lap must all be present then.         */
+ * Returns 0, or -1 for bad arguments.  With a k-point the Bloch factor of
+ * grad needs val, and that of lap needs val and grad; values only is fine. */
 int oracle_eval(const double lattice[9], int n1, int n2, int n3, int norb,
                 const void* coef, int kind, const double* kvec,
                 const double* pos, int64_t npos,
@@ -297,7 +297,8 @@ int oracle_eval(const double lattice[9], int n1, int n2, int n3, int norb,
     if (n1 < 1 || n2 < 1 || n3 < 1 || norb < 1 || npos < 0) return -1;
     if (kind < ORC_F64 || kind > ORC_C64) return -1;
     if (kvec && (kind == ORC_F64 || kind == ORC_F32)) return -1;
-    if (kvec && (!val || !grad || !lap)) return -1;
+    /* with a Bloch factor, grad needs u and lap needs u and grad u */
+    if (kvec && ((grad && !val) || (lap && (!val || !grad)))) return -1;
     if (oracle_inverse3(lattice, G) != 0) return -1;
     for (c = 0; c < 3; ++c)
         for (d = 0; d < 3; ++d) M[c * 3 + d] = (double)n[d] * G[c * 3 + d];

@@ -367,3 +367,21 @@ def test_positions_are_independent(oracle_lib):
         oj = oracle_lib.evaluate(A, n, c, pos[j:j + 1])
         for k in ("val", "grad", "lap"):
             np.testing.assert_array_equal(oj[k][0], o[k][j])
+
+
+def test_bloch_values_only_equals_full_call(oracle_lib):
+    """With a k-point, asking for values only gives exactly the values of the
+    full call (the Bloch factor of the value uses the value alone), and a
+    gradient without the value is refused."""
+    rng = np.random.default_rng(zlib.crc32(b"bloch-values-only"))
+    n = (6, 7, 5)
+    L = 4
+    A = np.array([[5.0, 0.4, 0.0], [0.1, 4.0, 0.3], [0.0, -0.2, 6.0]])
+    coef = (rng.uniform(-1, 1, n + (L,)) + 1j * rng.uniform(-1, 1, n + (L,))).astype(np.complex128)
+    k = np.array([0.3, -0.2, 0.5])
+    pos = rng.uniform(-3, 9, (11, 3))
+    full = oracle_lib.evaluate(A, n, coef, pos, kvec=k)
+    vo = oracle_lib.evaluate(A, n, coef, pos, kvec=k, want=("val",))
+    np.testing.assert_array_equal(vo["val"], full["val"])
+    with pytest.raises(ValueError):
+        oracle_lib.evaluate(A, n, coef, pos, kvec=k, want=("grad",))
