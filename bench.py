@@ -114,30 +114,79 @@ def time_launches(fn, blocks, steps, warmup, stream, pre=None):
     return wall, durs
 
 
-def cpu_baseline(spec, coef, npos, budget_s=12.0):
-    """FP64 oracle on a bounded sample of the same workload, all host cores:
-    whole move blocks of the benchmark's shape, as many as fit ~budget_s."""
-    import oracle
-    from paper_1204_1121_amd import workloads as wl
-    threads = len(os.sched_getaffinity(0))
-    L = spec.norb
-    # calibrate on one block, then size the sample to ~budget_s
-    first = wl.move_block(spec, npos, block=1000)
-    t0 = time.perf_counter()
-    oracle.evaluate(spec.lattice, spec.n, coef, first, nthreads=threads)
-    dt1 = max(time.perf_counter() - t0, 1e-6)
-    nblk = int(max(1, min(256, budget_s / dt1)))
-    sample = np.concatenate([wl.move_block(spec, npos, block=1000 + b) for b in range(nblk)])
-    t0 = time.perf_counter()
-    oracle.evaluate(spec.lattice, spec.n, coef, sample, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": sample.shape[0] * L / dt, "unit": UNIT, "cores": threads,
-            "kind": "oracle",
-            "sample": f"{nblk} move blocks of {npos} positions ({sample.shape[0]} positions "
-                      f"x {L} orbitals, val+grad+lap, FP64): {dt:.1f} s on {threads} threads"}
+class CpuBaselineLeg:
+    """The CPU-baseline leg: every use of the FP64 oracle in this file goes
+    through this object (timings of the oracle on the host cores, and the FP64
+    reference values that the precision figures are measured against).  With
+    --no-cpu-baseline it is not created and none of those figures appear."""
+
+    def __init__(self):
+        import oracle
+        from oracle import slater
+        self.oracle = oracle
+        self.slater = slater
+        self.threads = len(os.sched_getaffinity(0))
+        self.cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        self.cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+
+    def blocks(self, spec, coef, npos, budget_s=12.0):
+        """FP64 oracle on a bounded sample of the same workload, all host
+        cores: whole move blocks of the benchmark's shape, as many as fit
+        ~budget_s; plus one block on one core (the paper's CPU baseline)."""
+        from paper_1204_1121_amd import workloads as wl
+        L = spec.norb
+        first = wl.move_block(spec, npos, block=1000)
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, first, nthreads=1)
+        dt_one = max(time.perf_counter() - t0, 1e-6)
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, first, nthreads=self.threads)
+        dt1 = max(time.perf_counter() - t0, 1e-6)
+        nblk = int(max(1, min(256, budget_s / dt1)))
+        sample = np.concatenate([wl.move_block(spec, npos, block=1000 + b) for b in range(nblk)])
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, sample, nthreads=self.threads)
+        dt = time.perf_counter() - t0
+        return {"value": sample.shape[0] * L / dt, "unit": UNIT, "cores": self.threads,
+                "kind": "oracle", "cpu": self.cpu_model,
+                "sample": f"{nblk} move blocks of {npos} positions ({sample.shape[0]} positions "
+                          f"x {L} orbitals, val+grad+lap, FP64): {dt:.1f} s on "
+                          f"{self.threads} threads",
+                "single_core": {"value": npos * L / dt_one, "unit": UNIT, "cores": 1,
+                                "sample": f"one block of {npos} positions: {dt_one:.2f} s"}}
+
+    def reference(self, spec, coef, pos, want=("val", "grad", "lap")):
+        """FP64 oracle values at pos (all host cores)."""
+        return self.oracle.evaluate(spec.lattice, spec.n, coef, pos, kvec=spec.kvec, want=want,
+                                    nthreads=self.threads)
+
+    def time_values(self, spec, coef, pos, nthreads=1):
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, pos, kvec=spec.kvec, want=("val",),
+                             nthreads=nthreads)
+        return time.perf_counter() - t0
+
+    def time_sm(self, inv_t, u_rows, cols):
+        t0 = time.perf_counter()
+        self.slater.sm_update(inv_t, u_rows, cols)
+        return time.perf_counter() - t0
+
+    def blas_threads(self):
+        try:
+            from threadpoolctl import threadpool_info
+            return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            return 1
 
 
-def bench_sm(args, with_cpu):
+def bench_sm(args, leg=None):
     """Sherman-Morrison update of one spin's inverse after a quasi-simultaneous
     step: n = 768 electrons (one spin of the TiO2 block), K = 384 accepted
     moves (half), in electron order.  Synthetic matrix D = 2I + N(0, 1/n)
@@ -172,17 +221,9 @@ def bench_sm(args, with_cpu):
                         "unit": "TFLOP/s", "frac": flop / t / 1e12 / FP64_PEAK_TFLOPS},
            "b_passes": {"blocked": launches, "rank1_per_move": 2 * K},
            "inputs": "D = 2I + N(0,1/n), new rows D + N(0,0.09) in FP32, 384 of 768 moved"}
-    if with_cpu:
-        from oracle import slater
-        t0 = time.perf_counter()
-        slater.sm_update(inv_t, U[cols].astype(np.float64), cols)
-        dt = time.perf_counter() - t0
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:
-            cores = 1
-        res["cpu_baseline"] = {"value": K / dt, "unit": "moves/s", "cores": cores,
+    if leg is not None:
+        dt = leg.time_sm(inv_t, U[cols].astype(np.float64), cols)
+        res["cpu_baseline"] = {"value": K / dt, "unit": "moves/s", "cores": leg.blas_threads(),
                                "kind": "oracle",
                                "sample": f"one step of {K} moves at n = {n}: {dt:.2f} s"}
     return res
@@ -328,18 +369,17 @@ def bench_serving(args):
     return out
 
 
-def bench_precision(args, real_coef, real_spec, cache):
+def bench_precision(args, real_coef, real_spec, cache, leg=None):
     """Storage dtypes at 1,536 positions: the complex k-point table (384
     orbitals) as complex64 / BF16 pairs / FP16 pairs, and the 768-orbital real
     table as FP32 / BF16 / FP16.  For each: kernel time, evals/s and the
     normwise max relative error of val, grad and lap against the FP64 oracle
-    on the FP32 master, over the whole block."""
+    on the FP32 master, over the whole block (errors only with the CPU-baseline
+    leg, which supplies the oracle's values)."""
     import torch
-    import oracle
     from paper_1204_1121_amd import blip
     from paper_1204_1121_amd import workloads as wl
     stream = torch.cuda.current_stream()
-    threads = len(os.sched_getaffinity(0))
     out = {}
     cases = [("complex_k", wl.spec_tio2_complex(), None, ("c64", "cbf16", "cf16")),
              ("real", real_spec, real_coef, ("f32", "bf16", "f16"))]
@@ -348,7 +388,7 @@ def bench_precision(args, real_coef, real_spec, cache):
             coef = wl.coefficients(spec)
         blocks = [torch.from_numpy(wl.move_block(spec, 1536, block=b)).cuda() for b in range(NROT)]
         pos0 = wl.move_block(spec, 1536, block=0)
-        ref = oracle.evaluate(spec.lattice, spec.n, coef, pos0, kvec=spec.kvec, nthreads=threads)
+        ref = leg.reference(spec, coef, pos0) if leg is not None else None
         for st in dtypes:
             t = blip.Table(spec.lattice, spec.n, coef, st, kvec=spec.kvec)
             o = t.alloc_outputs(1536)
@@ -357,19 +397,70 @@ def bench_precision(args, real_coef, real_spec, cache):
                 cache.put(t, 1536, False, best, note=f"blip_autotune rotate={NROT}")
             calls = {id(b): t.bind(b, o) for b in blocks}
             wall, tk = time_region(lambda b: calls[id(b)](), blocks, 100, 10, stream)
-            v, g, l = t.eval(blocks[0], out=o)
-            torch.cuda.synchronize()
-            got = {"val": v.cpu().numpy(), "grad": g.cpu().numpy(), "lap": l.cpu().numpy()}
-            err = {k: float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in ref}
             rb = t.info()["row_bytes"]
             shape = t.get_shape(1536)
-            out[f"{label}_{st}"] = {"kernel_us": tk * 1e6, "evals_per_s": 1536 * spec.norb / tk,
-                                   "row_bytes": rb, "max_rel_err": err,
-                                   "shape": {"tile_pos": shape[0], "vec": shape[1]}}
-            log(f"precision {label} {st}: {tk * 1e6:.1f} us, err val {err['val']:.1e} "
-                f"grad {err['grad']:.1e} lap {err['lap']:.1e}")
+            rec = {"kernel_us": tk * 1e6, "evals_per_s": 1536 * spec.norb / tk,
+                   "row_bytes": rb, "shape": {"tile_pos": shape[0], "vec": shape[1]}}
+            msg = ""
+            if ref is not None:
+                v, g, l = t.eval(blocks[0], out=o)
+                torch.cuda.synchronize()
+                got = {"val": v.cpu().numpy(), "grad": g.cpu().numpy(), "lap": l.cpu().numpy()}
+                err = {k: float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k])))
+                       for k in ref}
+                rec["max_rel_err"] = err
+                msg = f", err val {err['val']:.1e} grad {err['grad']:.1e} lap {err['lap']:.1e}"
+            out[f"{label}_{st}"] = rec
+            log(f"precision {label} {st}: {tk * 1e6:.1f} us{msg}")
             t.free()
     return out
+
+
+PAPER_SYSTEMS = (  # (system, electrons N, orbitals L, the paper's GPU ms per step, CPU ms)
+    ("Si 3x3x3", 216, 56, 0.17, 2.77),
+    ("TiO2 3x3x3", 648, 168, 0.82, 20.21),
+    ("TiO2 4x4x4", 1536, 384, 3.26, 100.00),
+)
+
+
+def bench_paper_sizes(args, leg=None):
+    """The paper's own workload shape (Table system_size): complex orbital
+    values only, one evaluation of all L orbitals at the N moved electrons of
+    a quasi-simultaneous step, for its three (N, L).  Synthetic complex64
+    tables on the 72x72x48 grid of the 18x18x12 bohr cell at the k-point of
+    the complex workload, so only N and L change between rows.  The paper's
+    GTX 480 times (kernel plus PCIe) and single-core CPU times are context."""
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    base = wl.spec_tio2_complex()
+    rows = []
+    for name, N, L, paper_gpu_ms, paper_cpu_ms in PAPER_SYSTEMS:
+        spec = wl.TableSpec(f"values_only_N{N}_L{L}c", base.lattice, base.n, L, complex_=True,
+                            kvec=base.kvec, seed=base.seed + L)
+        coef = wl.coefficients(spec)
+        t = blip.Table(spec.lattice, spec.n, coef, "c64", kvec=spec.kvec)
+        blocks = [torch.from_numpy(wl.move_block(spec, N, block=b)).cuda() for b in range(NROT)]
+        o = t.alloc_outputs(N, grad=False)
+        calls = {id(b): t.bind(b, o) for b in blocks}
+        _, tk = time_region(lambda b: calls[id(b)](), blocks, 200, 20, stream)
+        row = {"system": name, "N": N, "L": L, "kernel_us": tk * 1e6,
+               "complex_values_per_s": N * L / tk,
+               "paper_gtx480_ms_kernel_plus_pcie": paper_gpu_ms,
+               "paper_cpu_1core_ms": paper_cpu_ms}
+        msg = ""
+        if leg is not None:
+            pos0 = wl.move_block(spec, N, block=0)
+            dt = leg.time_values(spec, coef, pos0, nthreads=1)
+            row["oracle_1core_ms"] = dt * 1e3
+            row["speedup_vs_oracle_1core"] = dt / tk
+            msg = f", FP64 oracle on one core {dt * 1e3:.1f} ms ({dt / tk:.0f}x)"
+        rows.append(row)
+        log(f"paper size {name} (N={N}, L={L}, complex, values only): {tk * 1e6:.1f} us{msg}")
+        t.free()
+        del coef
+    return rows
 
 
 def copy_probe(nbytes=1 << 30, reps=5):
@@ -408,6 +499,8 @@ def main():
                     help="skip the Sherman-Morrison update figure")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the storage-dtype / complex k-point section")
+    ap.add_argument("--no-paper-sizes", action="store_true",
+                    help="skip the values-only complex section at the paper's system sizes")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving rate point")
     ap.add_argument("--copy-probe", action="store_true",
@@ -429,6 +522,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    leg = None if args.no_cpu_baseline else CpuBaselineLeg()
 
     spec = wl.spec_tio2()
     t0 = time.perf_counter()
@@ -541,7 +635,7 @@ def main():
             f"for the orbitals")
 
     if not args.no_sm:
-        result["sm_update"] = bench_sm(args, not args.no_cpu_baseline)
+        result["sm_update"] = bench_sm(args, leg)
         sm = result["sm_update"]
         log(f"sm_update: {sm['us_per_step']:.1f} us per step of {sm['accepted_moves']} moves at "
             f"n = {sm['n']} ({sm['launches_per_step']} launches), "
@@ -568,11 +662,17 @@ def main():
 
     if not args.no_precision:
         try:
-            result["precision"] = bench_precision(args, coef, spec, cache)
+            result["precision"] = bench_precision(args, coef, spec, cache, leg)
             if args.save_tuning:
                 cache.save(args.save_tuning)
         except Exception as e:
             result["precision"] = {"error": f"{type(e).__name__}: {e}"}
+
+    if not args.no_paper_sizes:
+        try:
+            result["paper_sizes"] = bench_paper_sizes(args, leg)
+        except Exception as e:
+            result["paper_sizes"] = {"error": f"{type(e).__name__}: {e}"}
 
     if not args.no_batched:
         try:
@@ -590,9 +690,9 @@ def main():
     if args.copy_probe:
         result["copy_probe"] = copy_probe()
 
-    if not args.no_cpu_baseline:
+    if leg is not None:
         log("timing the FP64 oracle on the host ...")
-        result["cpu_baseline"] = cpu_baseline(spec, coef, npos)
+        result["cpu_baseline"] = leg.blocks(spec, coef, npos)
     del coef
 
     print(json.dumps(result), flush=True)
