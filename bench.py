@@ -221,6 +221,28 @@ def bench_sm(args, leg=None):
                         "unit": "TFLOP/s", "frac": flop / t / 1e12 / FP64_PEAK_TFLOPS},
            "b_passes": {"blocked": launches, "rank1_per_move": 2 * K},
            "inputs": "D = 2I + N(0,1/n), new rows D + N(0,0.09) in FP32, 384 of 768 moved"}
+    # the batched form: the same step for 64 matrices (32 walkers x 2 spins)
+    # in one launch sequence, lists and counts on the device
+    nmat = 64
+    inv_b = torch.from_numpy(inv_t).cuda().unsqueeze(0).repeat(nmat, 1, 1).contiguous()
+    u_b = u.unsqueeze(0).repeat(nmat, 1, 1).contiguous()
+    acc = torch.from_numpy(np.tile(cols.astype(np.int32), (nmat, 1))).cuda()
+    cnt = torch.full((nmat,), K, dtype=torch.int32, device="cuda")
+    ws_b = torch.empty(blip.lib().blip_sm_batched_workspace_size(nmat, n), dtype=torch.uint8,
+                       device="cuda")
+    rat_b = torch.empty((nmat, K), dtype=torch.float64, device="cuda")
+
+    def step_b(_):
+        blip.sm_update_batched(inv_b, u_b, acc, cnt, K, ratios=rat_b, workspace=ws_b,
+                               stream=stream)
+    steps_b = max(5, min(args.steps // 10, 20))
+    _, tb = time_region(step_b, [None], steps_b, 2, stream)
+    res["batched"] = {"matrices": nmat, "us_per_step": tb * 1e6,
+                      "us_per_matrix_step": tb * 1e6 / nmat,
+                      "launches_per_step": 2 * ((K + 31) // 32) + 1,
+                      "tflops_fp64": nmat * flop / tb / 1e12,
+                      "frac_fp64_peak": nmat * flop / tb / 1e12 / FP64_PEAK_TFLOPS}
+    del inv_b, u_b, ws_b
     if leg is not None:
         dt = leg.time_sm(inv_t, U[cols].astype(np.float64), cols)
         res["cpu_baseline"] = {"value": K / dt, "unit": "moves/s", "cores": leg.blas_threads(),
@@ -639,7 +661,9 @@ def main():
         sm = result["sm_update"]
         log(f"sm_update: {sm['us_per_step']:.1f} us per step of {sm['accepted_moves']} moves at "
             f"n = {sm['n']} ({sm['launches_per_step']} launches), "
-            f"{sm['roofline']['achieved']:.2f} TFLOP/s FP64")
+            f"{sm['roofline']['achieved']:.2f} TFLOP/s FP64; batched {sm['batched']['matrices']} "
+            f"matrices: {sm['batched']['us_per_matrix_step']:.1f} us per matrix-step, "
+            f"{sm['batched']['tflops_fp64']:.2f} TFLOP/s")
 
     if not args.no_cold:
         # Cold Infinity Cache: read 1 GiB of unrelated data before every

@@ -314,6 +314,46 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
  * order n (0 if n is out of range). */
 BLIP_API size_t blip_sm_workspace_size(int64_t n);
 
+/*
+ * blip_sm_update_batched -- blip_sm_update for many matrices at once (the
+ * walkers and spins of a Monte Carlo step), with the accepted moves on the
+ * device, as a quasi-simultaneous step produces them (Sec. IV.A; the update
+ * of Sec. VI.D).
+ *
+ *  nmat        matrices, 0..65535; matrix q has order n (1..4096).
+ *  inv         device double: B of matrix q at inv + q * inv_mstride, row i
+ *              at + i * inv_ld (the layout of blip_sm_update); in place.
+ *  u           device float: the new orbitals of electron c of matrix q at
+ *              u + q * u_mstride + c * u_ld (u ordered by electron; n rows
+ *              per matrix, columns l < n read).
+ *  acc_cols    device int32 [nmat][acc_ld]: matrix q's accepted electrons in
+ *              the order the moves are applied; each electron at most once
+ *              per matrix (a quasi-simultaneous step moves each once).
+ *  acc_count   device int32 [nmat]: moves of matrix q, clamped to [0, max_k].
+ *  max_k       host bound on every count (0..n); sets the number of launches,
+ *              2 * ceil(max_k / 32) + 1, whatever the counts are.
+ *  ratios      device double [nmat][ratio_ld] or NULL: the sequential ratios,
+ *              slot m of matrix q for its move m.
+ *  workspace   blip_sm_batched_workspace_size(nmat, n) bytes, 8-byte aligned.
+ * Entries of acc_cols outside [0, n) are clamped into it: wrong input gives
+ * wrong results, never an out-of-bounds access; a repeated electron within a
+ * matrix gives wrong results.  The arithmetic and its order are exactly those
+ * of blip_sm_update on the same list, so the results are bitwise equal.
+ * Everything is read on the device and the launch sequence depends only on
+ * nmat, n and max_k: a step can be captured in a graph.  Asynchronous, no
+ * allocation.  BLIP_E_ARG / BLIP_E_ALIGN on host-checkable errors.
+ */
+BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t inv_mstride,
+                                    int64_t inv_ld, const float* u, int64_t u_mstride,
+                                    int64_t u_ld, const int32_t* acc_cols, int64_t acc_ld,
+                                    const int32_t* acc_count, int max_k, double* ratios,
+                                    int64_t ratio_ld, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
+/* blip_sm_batched_workspace_size -- bytes of workspace blip_sm_update_batched
+ * needs (0 if an argument is out of range). */
+BLIP_API size_t blip_sm_batched_workspace_size(int nmat, int64_t n);
+
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage,

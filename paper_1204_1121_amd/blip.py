@@ -91,6 +91,11 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_size_t, vp]
     L.blip_sm_workspace_size.restype = ctypes.c_size_t
     L.blip_sm_workspace_size.argtypes = [i64]
+    L.blip_sm_update_batched.restype = ci
+    L.blip_sm_update_batched.argtypes = [ci, i64, vp, i64, i64, vp, i64, i64, vp, i64, vp, ci,
+                                         vp, i64, vp, ctypes.c_size_t, vp]
+    L.blip_sm_batched_workspace_size.restype = ctypes.c_size_t
+    L.blip_sm_batched_workspace_size.argtypes = [ci, i64]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -398,6 +403,38 @@ def sm_update(inv: torch.Tensor, u: torch.Tensor, cols, u_row=None, ratios=None,
                                None if ur is None else ur.ctypes.data_as(ctypes.c_void_p),
                                c.size, _ptr(ratios), _ptr(workspace), workspace.numel(),
                                _stream_ptr(stream)))
+    return ratios
+
+
+def sm_update_batched(inv: torch.Tensor, u: torch.Tensor, acc_cols: torch.Tensor,
+                      acc_count: torch.Tensor, max_k: int, ratios=None, workspace=None,
+                      stream=None):
+    """Sherman-Morrison updates of many matrices in place
+    (blip_sm_update_batched).  inv: cuda float64 [nmat, n, >= n] (row i of
+    matrix q = column i of its D^{-1}); u: cuda float32 [nmat, n, >= n] (row c
+    = new orbitals of electron c); acc_cols: cuda int32 [nmat, >= max_k]
+    (accepted electrons in move order); acc_count: cuda int32 [nmat].
+    Returns the sequential ratios, cuda float64 [nmat, max_k]."""
+    nmat, n = inv.shape[0], inv.shape[1]
+    if inv.dtype != torch.float64 or inv.dim() != 3 or inv.stride(2) != 1 or inv.shape[2] < n:
+        raise ValueError("inv must be float64 [nmat, n, >= n] with unit column stride")
+    if (u.dtype != torch.float32 or u.dim() != 3 or u.stride(2) != 1 or u.shape[0] != nmat
+            or u.shape[1] < n or u.shape[2] < n):
+        raise ValueError("u must be float32 [nmat, >= n, >= n] with unit column stride")
+    if acc_cols.dtype != torch.int32 or acc_cols.dim() != 2 or acc_cols.stride(1) != 1:
+        raise ValueError("acc_cols must be int32 [nmat, >= max_k]")
+    if acc_count.dtype != torch.int32 or acc_count.numel() != nmat or not acc_count.is_contiguous():
+        raise ValueError("acc_count must be a contiguous int32 [nmat]")
+    if ratios is None:
+        ratios = torch.empty((nmat, max(int(max_k), 1)), dtype=torch.float64, device=inv.device)
+    if workspace is None:
+        nbytes = lib().blip_sm_batched_workspace_size(nmat, n)
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=inv.device)
+    check(lib().blip_sm_update_batched(nmat, n, _ptr(inv), inv.stride(0), inv.stride(1), _ptr(u),
+                                       u.stride(0), u.stride(1), _ptr(acc_cols),
+                                       acc_cols.stride(0), _ptr(acc_count), int(max_k),
+                                       _ptr(ratios), ratios.stride(0), _ptr(workspace),
+                                       workspace.numel(), _stream_ptr(stream)))
     return ratios
 
 

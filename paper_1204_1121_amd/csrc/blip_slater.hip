@@ -35,7 +35,8 @@ namespace {
 
 constexpr int kSmChunk = 32;        // moves applied per launch
 constexpr int kSmThreads = 256;     // four waves
-constexpr int kSmRows = 8;          // rows of B per workgroup
+constexpr int kSmRows = 8;          // rows of B per workgroup (one matrix: more workgroups)
+constexpr int kSmRowsBatched = 16;  // rows per workgroup when many matrices fill the chip
 constexpr int kSmPiece = 128;       // columns per pass inside a column tile
 constexpr int kSmPad = kSmChunk + 1;
 constexpr int64_t kSmMaxN = 4096;
@@ -59,6 +60,18 @@ struct SmArgs {
     int colp[kSmChunk];  // electrons of the applied chunk, in move order
     int coln[kSmChunk];  // electrons of the next chunk
     int urow[kSmChunk];  // rows of u holding the next chunk's new orbitals
+    // Batched launches (blockIdx.z = matrix).  The chunk sizes and electron
+    // lists come from device memory; the offsets above are per matrix.
+    int chunk;               // this launch applies chunk-1 and prepares chunk
+    int max_k;               // moves per matrix are clamped to [0, max_k]
+    const int* acc_cols;     // [nmat][acc_ld] electrons in move order
+    int64_t acc_ld;
+    const int* acc_count;    // [nmat] moves per matrix
+    int64_t inv_mstride;     // elements between matrices in inv
+    int64_t u_mstride;       // elements between matrices in u
+    int64_t ws_mstride;      // doubles between matrices in the workspace
+    int64_t ratio_ld;        // ratios of matrix q start at ratio + q * ratio_ld
+    const double* sinv;      // [nmat] S^{-1} of the applied chunk, from sm_sinv_kernel
 };
 
 // Column tiles: at most kSmMaxTiles per row (so summing V's partials stays
@@ -74,87 +87,246 @@ inline SmShape sm_shape(int64_t n)
     return {(int)tl, (int)((n + tl - 1) / tl)};
 }
 
-// What a thread reads for one kSmPiece-wide pass: its column of B on its four
+// Per-matrix workspace of the batched form: V partials and R for two chunks,
+// then S^{-1} of the applied chunk (padded rows).
+constexpr int64_t kSinvDoubles = kSmChunk * kSmPad;
+
+inline int64_t sm_ws_doubles(int64_t n)
+{
+    const SmShape sh = sm_shape(n);
+    const int64_t d = 2 * ((int64_t)sh.nct + 1) * kSmChunk * n + kSinvDoubles;
+    return (d + 31) / 32 * 32;   // keep each matrix's block 256-byte aligned
+}
+
+// What a thread reads for one kSmPiece-wide pass: its column of B on its RPT
 // rows, the chunk's moved rows R at that column, and (for the next chunk) 16
 // new-orbital values at that column.  Loaded together so their latencies
 // overlap.
+template <int RPT>
 struct SmFrag {
-    double b[4];
+    double b[RPT];
     double r[kSmChunk];
     float u[16];
 };
 
+// Moves of matrix q in a batched launch: kp of chunk c-1 and kn of chunk c.
+__device__ __forceinline__ void sm_batched_counts(const SmArgs& a, int q, int& kp, int& kn)
+{
+    int cnt = a.acc_count[q];
+    cnt = cnt < 0 ? 0 : (cnt > a.max_k ? a.max_k : cnt);
+    const int lo = (a.chunk - 1) * kSmChunk, hi = a.chunk * kSmChunk;
+    kp = a.chunk > 0 ? min(max(cnt - lo, 0), kSmChunk) : 0;
+    kn = min(max(cnt - hi, 0), kSmChunk);
+}
+
+// Electron m of chunk ch of matrix q (clamped into [0, n): bad lists give
+// wrong results, never out-of-bounds accesses).
+__device__ __forceinline__ int sm_batched_col(const SmArgs& a, int q, int ch, int m)
+{
+    const int c = a.acc_cols[(int64_t)q * a.acc_ld + (int64_t)ch * kSmChunk + m];
+    return c < 0 ? 0 : (c >= a.n ? a.n - 1 : c);
+}
+
+// S = V[c_m][m'] of the applied chunk, the column-tile partials summed in a
+// fixed order; unused rows and columns hold the identity.  Thread t gets
+// S[t/32 + 8j][t%32], j < 4.
+__device__ __forceinline__ void sm_build_s(const double* __restrict__ Pp, int n, int nct, int kp,
+                                           const int* lcolp, int tid, double (&sv)[4])
+{
+    const int gc = tid % kSmChunk;
+    const int gr0 = tid / kSmChunk;
+    double part[4][kSmMaxTiles];
+    const int cq = gc < kp ? gc : kp - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = gr0 + 8 * j;
+        const int row = lcolp[r < kp ? r : kp - 1];
+#pragma unroll
+        for (int t = 0; t < kSmMaxTiles; ++t)
+            part[j][t] = Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + cq];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = gr0 + 8 * j;
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? part[j][t] : 0.0;
+        sv[j] = (r < kp && gc < kp) ? v : (r == gc ? 1.0 : 0.0);
+    }
+}
+
+// S^{-1} by Gauss-Jordan without pivoting, in registers (the layout of
+// sm_build_s).  Each step publishes pivot row p and column p through
+// double-buffered LDS vectors (one barrier); every thread then reads what it
+// needs in one round trip and updates its 4 entries.  piv[p] receives the
+// pivots, the sequential ratios.  Ends with S^{-1} in Sinv (after a barrier).
+__device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
+                                             double (*bc)[2][kSmChunk], double* piv,
+                                             double (*Sinv)[kSmPad])
+{
+    const int gc = tid % kSmChunk;
+    const int gr0 = tid / kSmChunk;
+    for (int p = 0; p < kp; ++p) {
+        const int b = p & 1;
+        const int jp = p >> 3;
+        if (gr0 == (p & 7)) bc[b][0][gc] = jp == 0 ? sv[0] : jp == 1 ? sv[1] : jp == 2 ? sv[2] : sv[3];
+        if (gc == p) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bc[b][1][gr0 + 8 * j] = sv[j];
+        }
+        __syncthreads();
+        const double d = bc[b][0][p];
+        const double rowv = bc[b][0][gc];
+        double crp[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) crp[j] = bc[b][1][gr0 + 8 * j];
+        const double rd = 1.0 / d;
+        // column p becomes -S[r][p]/d, row p becomes S[p][c]/d (1/d on the
+        // diagonal), the rest S[r][c] - S[r][p] S[p][c]/d
+        const bool pcol = (gc == p);
+        const double coef = pcol ? rd : rowv * rd;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double nv = fma(-crp[j], coef, pcol ? 0.0 : sv[j]);
+            sv[j] = (gr0 + 8 * j == p) ? coef : nv;
+        }
+        if (tid == 0) piv[p] = d;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Sinv[gr0 + 8 * j][gc] = sv[j];
+    __syncthreads();
+}
+
+// Batched form only: S^{-1} of chunk (chunk-1) of matrix blockIdx.x, and its
+// pivots written to the matrix's ratios.  One workgroup per matrix, so the
+// main launch that follows does not eliminate S in every workgroup.
+__global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
+{
+    __shared__ double bc[2][2][kSmChunk];
+    __shared__ double Sinv[kSmChunk][kSmPad];
+    __shared__ double piv[kSmChunk];
+    __shared__ int lcolp[kSmChunk];
+    const int q = blockIdx.x;
+    const int tid = threadIdx.x;
+    int kp, kn;
+    sm_batched_counts(a, q, kp, kn);
+    if (kp == 0) return;   // uniform over the workgroup
+    if (tid < kSmChunk) lcolp[tid] = sm_batched_col(a, q, a.chunk - 1, tid < kp ? tid : kp - 1);
+    __syncthreads();
+    const double* Pp = a.Pp + q * a.ws_mstride;
+    double sv[4];
+    sm_build_s(Pp, a.n, a.nct, kp, lcolp, tid, sv);
+    sm_eliminate(kp, tid, sv, bc, piv, Sinv);
+    double* out = const_cast<double*>(a.sinv) + q * a.ws_mstride;
+    for (int e = tid; e < kSmChunk * kSmPad; e += kSmThreads) out[e] = (&Sinv[0][0])[e];
+    if (a.ratio != nullptr && tid < kp)
+        a.ratio[(int64_t)q * a.ratio_ld + (int64_t)(a.chunk - 1) * kSmChunk + tid] = piv[tid];
+}
+
 // One launch: workgroup (x, y) applies chunk p to rows [8x, 8x+8) and
 // columns [y*tl, (y+1)*tl) of B, copies the moved rows of chunk n into Rn,
-// and writes its columns' share of V = B' U^T for chunk n to Pn[y].
+// and writes its columns' share of V = B' U^T for chunk n to Pn[y].  In the
+// batched form blockIdx.z is the matrix and S^{-1} comes from sm_sinv_kernel.
 //
 // Loads are written without data-dependent branches: addresses are clamped
 // into bounds and unwanted values replaced by zero afterwards, so each group
 // of loads is issued back to back and waited for once.  Only the uniform
 // tests kp > 0 and kn > 0 guard buffers that may be absent.
+template <bool BATCHED, int ROWS>
 __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
 {
+    constexpr int RPT = ROWS / 2;          // rows per thread in the update
+    constexpr int VPT = ROWS / 8;          // entries of V (and Y) per thread
     __shared__ double bc[2][2][kSmChunk];       // pivot row / column, double-buffered
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
-    __shared__ double Vl[kSmRows][kSmChunk];    // rows of V - E of this tile
-    __shared__ double Y[kSmRows][kSmChunk];     // rows of (V - E) S^{-1}
+    __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
+    __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
     __shared__ double piv[kSmChunk];
-    __shared__ double Bt[kSmRows][kSmPiece];    // updated piece of B
+    __shared__ double Bt[ROWS][kSmPiece];       // updated piece of B
     __shared__ float Ut[kSmPiece][kSmPad];      // piece of U^T of the next chunk
-    __shared__ int lcolp[kSmChunk], lcoln[kSmChunk];
-    __shared__ int slot[kSmRows];               // row's index in the next chunk, or -1
+    __shared__ int lcolp[kSmChunk], lcoln[kSmChunk], lurow[kSmChunk];
+    __shared__ int slot[ROWS];                  // row's index in the next chunk, or -1
 
     const int tid = threadIdx.x;
     const int n = a.n;
-    const int kp = a.kp;
-    const int kn = a.kn;
     const int nct = a.nct;
-    const int i0 = blockIdx.x * kSmRows;
+    int kp = a.kp, kn = a.kn;
+    double* inv = a.inv;
+    const float* u = a.u;
+    const double* Pp = a.Pp;
+    const double* Rp = a.Rp;
+    double* Pn = a.Pn;
+    double* Rn = a.Rn;
+    const int q = BATCHED ? (int)blockIdx.z : 0;
+    if constexpr (BATCHED) {
+        sm_batched_counts(a, q, kp, kn);
+        if (kp == 0 && kn == 0) return;   // nothing for this matrix in this launch
+        inv += q * a.inv_mstride;
+        u += q * a.u_mstride;
+        const int64_t wo = q * a.ws_mstride;
+        Pp += wo;
+        Rp += wo;
+        Pn += wo;
+        Rn += wo;
+    }
+    const int i0 = blockIdx.x * ROWS;
     const int c0 = blockIdx.y * a.tl;
     const int cend = min(n, c0 + a.tl);
     const int cc = tid % kSmPiece;                                  // column within a piece
-    const int h = __builtin_amdgcn_readfirstlane(tid / kSmPiece);   // rows 4h..4h+3 (per wave)
+    const int h = __builtin_amdgcn_readfirstlane(tid / kSmPiece);   // rows RPT*h.. (per wave)
 
-    // index lists into LDS (uniform reads of the arguments, one select each)
-    if (tid < kSmChunk) {
-        int cp = 0, cn = 0;
-#pragma unroll
-        for (int m = 0; m < kSmChunk; ++m) {
-            cp = (tid == m) ? a.colp[m] : cp;
-            cn = (tid == m) ? a.coln[m] : cn;
+    // index lists into LDS
+    if constexpr (BATCHED) {
+        if (tid < kSmChunk) {
+            lcolp[tid] = kp > 0 ? sm_batched_col(a, q, a.chunk - 1, tid < kp ? tid : kp - 1) : 0;
+            const int cn = kn > 0 ? sm_batched_col(a, q, a.chunk, tid < kn ? tid : kn - 1) : 0;
+            lcoln[tid] = cn;
+            lurow[tid] = cn;   // u is ordered by electron
         }
-        lcolp[tid] = cp;
-        lcoln[tid] = cn;
+    } else {
+        // uniform reads of the arguments, one select each
+        if (tid < kSmChunk) {
+            int cp = 0, cn = 0, ur = 0;
+#pragma unroll
+            for (int m = 0; m < kSmChunk; ++m) {
+                cp = (tid == m) ? a.colp[m] : cp;
+                cn = (tid == m) ? a.coln[m] : cn;
+                ur = (tid == m) ? a.urow[m] : ur;
+            }
+            lcolp[tid] = cp;
+            lcoln[tid] = cn;
+            lurow[tid] = ur;
+        }
     }
+    __syncthreads();
 
     // A lane whose column is past the tile reads the tile's last column (in
     // bounds) and its results are never stored; rows past n read row n-1.
     // Zeroing uses only uniform conditions, so no load sits behind a branch.
-    auto fetch = [&](int q0, SmFrag& f) {
+    auto fetch = [&](int q0, SmFrag<RPT>& f) {
         const int c = q0 + cc;
         const int cl = c < cend ? c : cend - 1;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int i = i0 + 4 * h + rr;   // uniform per wave
-            f.b[rr] = a.inv[(int64_t)(i < n ? i : n - 1) * a.ld + cl];
+        for (int rr = 0; rr < RPT; ++rr) {
+            const int i = i0 + RPT * h + rr;   // uniform per wave
+            f.b[rr] = inv[(int64_t)(i < n ? i : n - 1) * a.ld + cl];
         }
         if (kp > 0) {
 #pragma unroll
-            for (int m = 0; m < kSmChunk; ++m) f.r[m] = a.Rp[(int64_t)(m < kp ? m : kp - 1) * n + cl];
+            for (int m = 0; m < kSmChunk; ++m) f.r[m] = Rp[(int64_t)(m < kp ? m : kp - 1) * n + cl];
         }
         if (kn > 0) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int m = 16 * h + k;   // uniform per wave
-                f.u[k] = a.u[(int64_t)a.urow[m < kn ? m : kn - 1] * a.u_ld + cl];
+                f.u[k] = u[(int64_t)lurow[m < kn ? m : kn - 1] * a.u_ld + cl];
             }
         }
     };
-    SmFrag f;
+    SmFrag<RPT> f;
     fetch(c0, f);   // in flight while S is assembled and eliminated
-    __syncthreads();
 
-    if (tid < kSmRows) {
+    if (tid < ROWS) {
         int sl = -1;
         for (int m = 0; m < kn; ++m)
             if (lcoln[m] == i0 + tid) sl = m;
@@ -162,102 +334,64 @@ __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
     }
 
     if (kp > 0) {
-        // S (rows of V on the moved rows) and this tile's rows of V - E, each
-        // the column-tile partials summed in order; unused rows and columns
-        // of S hold the identity.  Thread t owns S[t/32 + 8j][t%32], j < 4.
-        const int gc = tid % kSmChunk;
-        const int gr0 = tid / kSmChunk;
-        double part[4][kSmMaxTiles];
+        // this tile's rows of V - E, the column-tile partials summed in order;
+        // thread t handles rows t/32 + 8k, k < VPT, at column t%32
+        const int vr0 = tid / kSmChunk, vm = tid % kSmChunk;
+        double vpart[VPT][kSmMaxTiles];
         {
-            const int cq = gc < kp ? gc : kp - 1;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = gr0 + 8 * j;
-                const int row = lcolp[r < kp ? r : kp - 1];
-#pragma unroll
-                for (int t = 0; t < kSmMaxTiles; ++t)
-                    part[j][t] = a.Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + cq];
-            }
-        }
-        double vpart[kSmMaxTiles];
-        const int vr = tid / kSmChunk, vm = tid % kSmChunk;
-        const int vi = i0 + vr;
-        {
-            const int row = vi < n ? vi : n - 1;
             const int mq = vm < kp ? vm : kp - 1;
 #pragma unroll
-            for (int t = 0; t < kSmMaxTiles; ++t)
-                vpart[t] = a.Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + mq];
-        }
-        double sv[4];
+            for (int k = 0; k < VPT; ++k) {
+                const int vi = i0 + vr0 + 8 * k;
+                const int row = vi < n ? vi : n - 1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = gr0 + 8 * j;
+                for (int t = 0; t < kSmMaxTiles; ++t)
+                    vpart[k][t] = Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + mq];
+            }
+        }
+        if constexpr (BATCHED) {
+            const double* src = a.sinv + q * a.ws_mstride;
+            for (int e = tid; e < kSmChunk * kSmPad; e += kSmThreads) (&Sinv[0][0])[e] = src[e];
+        } else {
+            double sv[4];
+            sm_build_s(Pp, n, nct, kp, lcolp, tid, sv);
+            sm_eliminate(kp, tid, sv, bc, piv, Sinv);
+        }
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int vi = i0 + vr0 + 8 * k;
             double v = 0.0;
 #pragma unroll
-            for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? part[j][t] : 0.0;
-            sv[j] = (r < kp && gc < kp) ? v : (r == gc ? 1.0 : 0.0);
-        }
-        {
-            double v = 0.0;
-#pragma unroll
-            for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? vpart[t] : 0.0;
+            for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? vpart[k][t] : 0.0;
             if (lcolp[vm] == vi && vm < kp) v -= 1.0;
-            Vl[vr][vm] = (vi < n && vm < kp) ? v : 0.0;
+            Vl[vr0 + 8 * k][vm] = (vi < n && vm < kp) ? v : 0.0;
         }
-
-        // S^{-1} by Gauss-Jordan without pivoting, in registers: thread t
-        // keeps S[t/32 + 8j][t%32], j < 4.  Each step publishes pivot row p
-        // and column p through double-buffered LDS vectors (one barrier);
-        // every thread then reads what it needs in one round trip and
-        // updates its 4 entries.  The pivots are the sequential ratios.
-        for (int p = 0; p < kp; ++p) {
-            const int b = p & 1;
-            const int jp = p >> 3;
-            if (gr0 == (p & 7)) bc[b][0][gc] = jp == 0 ? sv[0] : jp == 1 ? sv[1] : jp == 2 ? sv[2] : sv[3];
-            if (gc == p) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bc[b][1][gr0 + 8 * j] = sv[j];
-            }
-            __syncthreads();
-            const double d = bc[b][0][p];
-            const double rowv = bc[b][0][gc];
-            double crp[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) crp[j] = bc[b][1][gr0 + 8 * j];
-            const double rd = 1.0 / d;
-            // column p becomes -S[r][p]/d, row p becomes S[p][c]/d (1/d on
-            // the diagonal), the rest S[r][c] - S[r][p] S[p][c]/d
-            const bool pcol = (gc == p);
-            const double coef = pcol ? rd : rowv * rd;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const double nv = fma(-crp[j], coef, pcol ? 0.0 : sv[j]);
-                sv[j] = (gr0 + 8 * j == p) ? coef : nv;
-            }
-            if (tid == 0) piv[p] = d;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Sinv[gr0 + 8 * j][gc] = sv[j];
         __syncthreads();
-        {
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
             double y = 0.0;
-            for (int q = 0; q < kp; ++q) y = fma(Vl[vr][q], Sinv[q][vm], y);
-            Y[vr][vm] = (vm < kp) ? y : 0.0;
+            for (int p = 0; p < kp; ++p) y = fma(Vl[vr0 + 8 * k][p], Sinv[p][vm], y);
+            Y[vr0 + 8 * k][vm] = (vm < kp) ? y : 0.0;
         }
-        if (blockIdx.x == 0 && blockIdx.y == 0 && a.ratio != nullptr && tid < kp) a.ratio[tid] = piv[tid];
+        if constexpr (!BATCHED) {
+            if (blockIdx.x == 0 && blockIdx.y == 0 && a.ratio != nullptr && tid < kp) a.ratio[tid] = piv[tid];
+        }
     }
     __syncthreads();
 
     // Pieces of kSmPiece columns: B' = B - Y R, the moved rows of the next
     // chunk copied to Rn, then this piece's share of V = B' U^T.
-    const int vr = tid / kSmChunk, vm = tid % kSmChunk;   // V entry this thread sums
-    double vacc[4] = {0.0, 0.0, 0.0, 0.0};                 // four chains, added in order
+    const int vr0 = tid / kSmChunk, vm = tid % kSmChunk;   // V entries: rows vr0 + 8k
+    double vacc[VPT][4];                                    // four chains each, added in order
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vacc[k][t] = 0.0;
     for (int q0 = c0; q0 < cend; q0 += kSmPiece) {
         const int c = q0 + cc;
-        double acc[4];
+        double acc[RPT];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) acc[rr] = f.b[rr];
+        for (int rr = 0; rr < RPT; ++rr) acc[rr] = f.b[rr];
         if (kp > 0) {
             // all 32 terms: Y is zero past kp and the rows of f.r past kp are
             // clamped copies, so the loop has no branches and its LDS reads
@@ -265,21 +399,22 @@ __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
 #pragma unroll
             for (int m = 0; m < kSmChunk; ++m) {
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) acc[rr] = fma(-Y[4 * h + rr][m], f.r[m], acc[rr]);
+                for (int rr = 0; rr < RPT; ++rr) acc[rr] = fma(-Y[RPT * h + rr][m], f.r[m], acc[rr]);
             }
         }
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int r = 4 * h + rr;
+        for (int rr = 0; rr < RPT; ++rr) {
+            const int r = RPT * h + rr;
             const int i = i0 + r;
             if (c < cend && i < n) {
-                if (kp > 0) a.inv[(int64_t)i * a.ld + c] = acc[rr];
-                if (slot[r] >= 0) a.Rn[(int64_t)slot[r] * n + c] = acc[rr];
+                if (kp > 0) inv[(int64_t)i * a.ld + c] = acc[rr];
+                if (slot[r] >= 0) Rn[(int64_t)slot[r] * n + c] = acc[rr];
             }
         }
         if (kn > 0) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) Bt[4 * h + rr][cc] = (c < cend && i0 + 4 * h + rr < n) ? acc[rr] : 0.0;
+            for (int rr = 0; rr < RPT; ++rr)
+                Bt[RPT * h + rr][cc] = (c < cend && i0 + RPT * h + rr < n) ? acc[rr] : 0.0;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
                 Ut[cc][16 * h + k] = (c < cend && 16 * h + k < kn) ? f.u[k] : 0.0f;
@@ -290,22 +425,30 @@ __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
 #pragma unroll 4
             for (int j = 0; j < kSmPiece; j += 4) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) vacc[q] = fma(Bt[vr][j + q], (double)Ut[j + q][vm], vacc[q]);
+                for (int t = 0; t < 4; ++t) {
+                    const double uv = (double)Ut[j + t][vm];
+#pragma unroll
+                    for (int k = 0; k < VPT; ++k) vacc[k][t] = fma(Bt[vr0 + 8 * k][j + t], uv, vacc[k][t]);
+                }
             }
             __syncthreads();
         }
     }
     if (kn > 0) {
-        const int i = i0 + vr;
-        if (i < n && vm < kn)
-            a.Pn[((int64_t)blockIdx.y * n + i) * kSmChunk + vm] = (vacc[0] + vacc[1]) + (vacc[2] + vacc[3]);
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            const int i = i0 + vr0 + 8 * k;
+            if (i < n && vm < kn)
+                Pn[((int64_t)blockIdx.y * n + i) * kSmChunk + vm] =
+                    (vacc[k][0] + vacc[k][1]) + (vacc[k][2] + vacc[k][3]);
+        }
     }
 }
 
 hipError_t sm_launch(const SmArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)((a.n + kSmRows - 1) / kSmRows), (unsigned)a.nct);
-    hipLaunchKernelGGL(sm_chunk_kernel, grid, dim3(kSmThreads), 0, s, a);
+    hipLaunchKernelGGL((sm_chunk_kernel<false, kSmRows>), grid, dim3(kSmThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -404,6 +547,88 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
             a.Rn = R[c & 1];
         }
         hipError_t e = sm_launch(a, s);
+        if (e != hipSuccess) return fail_hip(e, "sm_chunk_kernel launch");
+    }
+    return BLIP_OK;
+}
+
+BLIP_API size_t blip_sm_batched_workspace_size(int nmat, int64_t n)
+{
+    if (nmat < 0 || n <= 0 || n > kSmMaxN) return 0;
+    return (size_t)nmat * (size_t)sm_ws_doubles(n) * sizeof(double);
+}
+
+BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t inv_mstride,
+                                    int64_t inv_ld, const float* u, int64_t u_mstride,
+                                    int64_t u_ld, const int32_t* acc_cols, int64_t acc_ld,
+                                    const int32_t* acc_count, int max_k, double* ratios,
+                                    int64_t ratio_ld, void* workspace, size_t workspace_bytes,
+                                    void* stream)
+{
+    if (nmat < 0 || nmat > 65535) return fail(BLIP_E_ARG, "nmat = %d outside [0, 65535]", nmat);
+    if (n < 1 || n > kSmMaxN) return fail(BLIP_E_ARG, "n = %lld outside [1, %lld]", (long long)n,
+                                          (long long)kSmMaxN);
+    if (max_k < 0 || max_k > n) return fail(BLIP_E_ARG, "max_k = %d outside [0, n]", max_k);
+    if (nmat == 0 || max_k == 0) return BLIP_OK;
+    if (inv == nullptr || u == nullptr || acc_cols == nullptr || acc_count == nullptr)
+        return fail(BLIP_E_ARG, "inv, u, acc_cols and acc_count are required");
+    if (inv_ld < n || u_ld < n || acc_ld < max_k || (ratios && ratio_ld < max_k))
+        return fail(BLIP_E_ARG, "inv_ld and u_ld must be >= n, acc_ld and ratio_ld >= max_k");
+    if (nmat > 1 && (inv_mstride < (n - 1) * inv_ld + n || u_mstride < (n - 1) * u_ld + n))
+        return fail(BLIP_E_ARG, "matrix strides smaller than one matrix");
+    if (!aligned(inv, 8) || !aligned(u, 4) || !aligned(acc_cols, 4) || !aligned(acc_count, 4) ||
+        (ratios && !aligned(ratios, 8)) || !aligned(workspace, 8))
+        return fail(BLIP_E_ALIGN, "inv, ratios and workspace need 8-byte, u and lists 4-byte "
+                                  "alignment");
+    const size_t need = blip_sm_batched_workspace_size(nmat, n);
+    if (workspace == nullptr || workspace_bytes < need)
+        return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
+
+    const SmShape sh = sm_shape(n);
+    const int64_t ws_m = sm_ws_doubles(n);
+    const size_t pv = (size_t)sh.nct * kSmChunk * n;
+    double* ws = static_cast<double*>(workspace);
+    double* V[2] = {ws, ws + pv};
+    double* R[2] = {ws + 2 * pv, ws + 2 * pv + (size_t)kSmChunk * n};
+    double* S = ws + 2 * pv + (size_t)2 * kSmChunk * n;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nchunks = (max_k + kSmChunk - 1) / kSmChunk;
+    const dim3 grid((unsigned)((n + kSmRowsBatched - 1) / kSmRowsBatched), (unsigned)sh.nct,
+                    (unsigned)nmat);
+
+    SmArgs a{};
+    a.n = (int)n;
+    a.tl = sh.tl;
+    a.nct = sh.nct;
+    a.inv = inv;
+    a.ld = inv_ld;
+    a.u = u;
+    a.u_ld = u_ld;
+    a.ratio = ratios;
+    a.max_k = max_k;
+    a.acc_cols = acc_cols;
+    a.acc_ld = acc_ld;
+    a.acc_count = acc_count;
+    a.inv_mstride = inv_mstride;
+    a.u_mstride = u_mstride;
+    a.ws_mstride = ws_m;
+    a.ratio_ld = ratio_ld;
+    a.sinv = S;
+    // launch c applies chunk c-1 (S^{-1} from the launch of sm_sinv_kernel
+    // just before it) and prepares chunk c
+    for (int c = 0; c <= nchunks; ++c) {
+        a.chunk = c;
+        if (c > 0) {
+            a.Pp = V[(c - 1) & 1];
+            a.Rp = R[(c - 1) & 1];
+            hipLaunchKernelGGL(sm_sinv_kernel, dim3((unsigned)nmat), dim3(kSmThreads), 0, s, a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail_hip(e, "sm_sinv_kernel launch");
+        }
+        a.Pn = V[c & 1];
+        a.Rn = R[c & 1];
+        hipLaunchKernelGGL((sm_chunk_kernel<true, kSmRowsBatched>), grid, dim3(kSmThreads), 0, s, a);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail_hip(e, "sm_chunk_kernel launch");
     }
     return BLIP_OK;

@@ -136,3 +136,35 @@ def test_sm_update_argument_errors(blip):
     assert call(c=okp, ratios=ctypes.c_void_p(0x10004)) == -5
     assert call(c=okp, w=ctypes.c_void_p(0x10004)) == -5
     assert call(c=None, k=0, w=None, wb=0) == 0          # k = 0: nothing to do
+
+
+def test_sm_update_batched_argument_errors(blip):
+    """blip_sm_update_batched checks sizes, strides, alignment and the
+    workspace on the host; nothing below reaches the device."""
+    L = blip.lib()
+    n = 64
+    ws = L.blip_sm_batched_workspace_size(3, n)
+    assert ws > 0 and ws % 256 == 0
+    assert L.blip_sm_batched_workspace_size(-1, n) == 0
+    assert L.blip_sm_batched_workspace_size(3, 4097) == 0
+    dev = ctypes.c_void_p(0x10000)            # never dereferenced
+
+    def call(nmat=3, n=n, inv=dev, ims=n * n, ild=n, u=dev, ums=n * n, uld=n, cols=dev, cld=n,
+             cnt=dev, max_k=n, ratios=dev, rld=n, w=dev, wb=ws):
+        return L.blip_sm_update_batched(nmat, n, inv, ims, ild, u, ums, uld, cols, cld, cnt, max_k,
+                                        ratios, rld, w, wb, None)
+
+    assert call(nmat=-1) == -1
+    assert call(nmat=70000) == -1
+    assert call(n=0) == -1 and call(n=4097) == -1
+    assert call(max_k=n + 1) == -1 and call(max_k=-1) == -1
+    assert call(inv=None) == -1 and call(cols=None) == -1 and call(cnt=None) == -1
+    assert call(ild=n - 1) == -1 and call(uld=n - 1) == -1
+    assert call(cld=n - 1) == -1 and call(rld=n - 1) == -1
+    assert call(ims=n * n - 1) == -1 and call(ums=n * n - 1) == -1
+    assert call(w=None) == -1 and call(wb=ws - 1) == -1
+    assert call(inv=ctypes.c_void_p(0x10004)) == -5
+    assert call(cols=ctypes.c_void_p(0x10002)) == -5
+    assert call(w=ctypes.c_void_p(0x10004)) == -5
+    assert call(nmat=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
+    assert call(max_k=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0

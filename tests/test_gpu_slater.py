@@ -185,3 +185,75 @@ def test_quasi_simultaneous_step_tio2(blip):
     got_b, got_r = check(blip, val_old, inv_t, cols, to_np(U), label="TiO2")
     assert got_r[0] == pytest.approx(qs[cols[0]], rel=1e-10)
     t.free()
+
+
+def test_batched_equals_single_bitwise(blip):
+    """blip_sm_update_batched over matrices with 0, 1, 31, 32, 70 and all 101
+    accepted moves equals blip_sm_update on each matrix bit for bit (same
+    arithmetic in the same order), ratios included; one matrix against the
+    oracle."""
+    n = 101
+    counts = [0, 1, 31, 32, 70, 101]
+    nmat = len(counts)
+    rng = np.random.default_rng(21)
+    Ds, invs, Us, lists = [], [], [], []
+    for q in range(nmat):
+        D, inv_t, _, U = case(300 + q, n, 1)
+        Ds.append(D)
+        invs.append(inv_t)
+        Us.append(U)
+        lists.append(rng.permutation(n)[: counts[q]].astype(np.int64))
+    max_k = max(counts)
+    acc = np.zeros((nmat, max_k), dtype=np.int32)
+    for q, c in enumerate(lists):
+        acc[q, : len(c)] = c
+    inv_b = torch.from_numpy(np.stack(invs)).cuda()
+    u_b = torch.from_numpy(np.stack(Us)).cuda()
+    say(f"batched SM: {nmat} matrices, counts {counts}")
+    r_b = blip.sm_update_batched(inv_b, u_b, torch.from_numpy(acc).cuda(),
+                                 torch.tensor(counts, dtype=torch.int32, device="cuda"), max_k)
+    torch.cuda.synchronize()
+    got_inv, got_r = to_np(inv_b), to_np(r_b)
+    for q in range(nmat):
+        inv1 = torch.from_numpy(invs[q]).cuda()
+        r1 = blip.sm_update(inv1, torch.from_numpy(Us[q]).cuda(), lists[q])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got_inv[q], to_np(inv1), err_msg=f"matrix {q}")
+        np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
+    q = 4
+    want_b, want_r = slater.sm_update(invs[q], Us[q][lists[q]].astype(np.float64), lists[q])
+    assert np.abs(got_inv[q] - want_b).max() <= 1e-10 * np.abs(want_b).max()
+    np.testing.assert_allclose(got_r[q, : counts[q]], want_r, rtol=1e-9)
+
+
+def test_batched_padded_strides_and_untouched(blip):
+    """Matrices with padded rows inside a wider buffer, u with extra rows:
+    columns past n and matrices with no moves are left as they were."""
+    n, nmat = 40, 3
+    counts = [5, 0, 40]
+    rng = np.random.default_rng(22)
+    base = np.full((nmat, n, 48), 9.0)
+    U = np.zeros((nmat, n + 3, 44), dtype=np.float32)
+    invs, lists = [], []
+    for q in range(nmat):
+        D, inv_t, _, Uq = case(400 + q, n, 1)
+        base[q, :, :n] = inv_t
+        U[q, :n, :n] = Uq
+        invs.append((inv_t, Uq))
+        lists.append(rng.permutation(n)[: counts[q]].astype(np.int64))
+    acc = np.zeros((nmat, 40), dtype=np.int32)
+    for q, c in enumerate(lists):
+        acc[q, : len(c)] = c
+    t = torch.from_numpy(base).cuda()
+    inv = t[:, :, :n]
+    r = blip.sm_update_batched(inv, torch.from_numpy(U).cuda(), torch.from_numpy(acc).cuda(),
+                               torch.tensor(counts, dtype=torch.int32, device="cuda"), 40)
+    torch.cuda.synchronize()
+    full = t.cpu().numpy()
+    assert np.all(full[:, :, n:] == 9.0)
+    np.testing.assert_array_equal(full[1, :, :n], invs[1][0])
+    for q in (0, 2):
+        want_b, want_r = slater.sm_update(invs[q][0], invs[q][1][lists[q]].astype(np.float64),
+                                          lists[q])
+        assert np.abs(full[q, :, :n] - want_b).max() <= 1e-10 * np.abs(want_b).max()
+        np.testing.assert_allclose(to_np(r)[q, : counts[q]], want_r, rtol=1e-9)
