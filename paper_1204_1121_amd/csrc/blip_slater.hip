@@ -22,6 +22,13 @@
 // column tile, which the next launch adds in a fixed order.  So a step of K
 // accepted moves takes ceil(K/32)+1 launches, and each launch reads and
 // writes B once.
+//
+// Two entry points share these kernels.  blip_sm_update serves one matrix
+// and is latency-bound: every workgroup eliminates S itself, which costs less
+// than another launch.  blip_sm_update_batched serves many matrices (walkers
+// and spins): a workgroup per matrix eliminates S once (sm_sinv_kernel), and
+// the chunk kernel's workgroups, 16 rows each, read S^{-1}.  Both run the
+// same arithmetic in the same order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
