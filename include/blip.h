@@ -220,8 +220,10 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
                            blip_tune_result* best);
 
 /* blip_set_shape / blip_get_shape -- set or read the launch shape used for
- * npos's size bucket (batched != 0: the batched path), e.g. to restore a
- * cached autotuning result. */
+ * npos's size bucket, the power-of-two range [2^k, 2^(k+1)) holding npos
+ * (batched != 0: the batched path), e.g. to restore a cached autotuning
+ * result.  A size whose bucket has no shape of its own uses one set for an
+ * adjacent bucket (the larger if both are), else the built-in default. */
 BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec);
 BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec);
 

@@ -126,16 +126,28 @@ static void bucket(int64_t npos, int64_t& lo, int64_t& hi)
     hi = lo * 2 - 1;
 }
 
+// The tuned shape of npos's bucket; failing that, one tuned for an adjacent
+// bucket (a batch just under a power of two keeps the shape tuned just above
+// it); failing that, the default.
 void choose_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
 {
     {
         std::lock_guard<std::mutex> lk(t->tune_mu);
+        const TuneEntry* near = nullptr;
         for (const TuneEntry& e : t->tune[mode]) {
             if (npos >= e.lo && npos <= e.hi) {
                 P = e.P;
                 OE = e.OE;
                 return;
             }
+            const bool adjacent = (npos < e.lo && npos >= e.lo / 2) ||
+                                  (npos > e.hi && npos <= 2 * e.hi + 1);
+            if (adjacent && (near == nullptr || e.lo > near->lo)) near = &e;
+        }
+        if (near != nullptr) {
+            P = near->P;
+            OE = near->OE;
+            return;
         }
     }
     default_shape(t, mode, npos, P, OE);
