@@ -17,6 +17,8 @@ Two independent formulations live here:
   the FP64 dot product of the orbitals with a column of the old inverse.
 * :mod:`oracle.slater` -- the sequential Sherman-Morrison update of the
   inverse Slater matrix after accepted moves, in NumPy.
+* :mod:`oracle.vmc` -- Monte Carlo steps on a synthetic Slater determinant:
+  a quasi-simultaneous step and a configuration-by-configuration sweep.
 
 Inputs are NumPy arrays; outputs are float64 (complex128 for complex tables).
 """
