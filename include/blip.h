@@ -356,6 +356,40 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
  * needs (0 if an argument is out of range). */
 BLIP_API size_t blip_sm_batched_workspace_size(int nmat, int64_t n);
 
+/*
+ * Quasi-simultaneous Monte Carlo step helpers (Sec. IV.A; the step of Sec.
+ * II.B: trial move, ratio, accept/reject, local energy).  Matrices are
+ * (walker, spin) pairs q = 2 * walker + spin with n electrons each; arrays
+ * indexed by electron are [nmat][n] (positions [nmat][n][3], bohr), so
+ * electron j of matrix q is entry q * n + j.  All device pointers; all
+ * asynchronous on the stream, no allocation.
+ *
+ * blip_qs_propose -- trial[p] = pos[p] + eta[p] for npos positions (the
+ *   random displacements are the caller's).
+ *
+ * blip_qs_accept -- for every matrix, candidates j in [j0, j1) (all n for a
+ *   quasi-simultaneous step; one electron for a configuration-by-
+ *   configuration move): accepted when uniform < ratio^2, the Metropolis test
+ *   for p = |Psi|^2 with the ratio of blip_eval_ratio against the old
+ *   configuration (a NaN ratio is rejected).  Accepted electrons get
+ *   pos = trial and are listed in increasing order in acc_cols[q * acc_ld ..]
+ *   with acc_count[q] entries: the inputs of blip_sm_update_batched.
+ *   acc_ld >= n; nmat <= 65535.
+ *
+ * blip_qs_kinetic -- e_kin[w] = -1/2 sum_{j < nel} lap_ratio[w * nel + j]:
+ *   the local kinetic energy of walker w from the Laplacian ratios of
+ *   blip_eval_ratio at its current positions against its current inverses
+ *   (sum_l lap psi_l(r_j) Dinv[l, j] = lap_j Psi_D / Psi_D), summed in a fixed
+ *   order.  nwalk <= 65535.
+ */
+BLIP_API int blip_qs_propose(int64_t npos, const double* pos, const double* eta, double* trial,
+                             void* stream);
+BLIP_API int blip_qs_accept(int nmat, int n, int j0, int j1, const double* ratio,
+                            const double* uniform, const double* trial, double* pos,
+                            int32_t* acc_cols, int64_t acc_ld, int32_t* acc_count, void* stream);
+BLIP_API int blip_qs_kinetic(int nwalk, int nel, const double* lap_ratio, double* e_kin,
+                             void* stream);
+
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage,

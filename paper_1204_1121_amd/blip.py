@@ -96,6 +96,12 @@ def lib() -> ctypes.CDLL:
                                          vp, i64, vp, ctypes.c_size_t, vp]
     L.blip_sm_batched_workspace_size.restype = ctypes.c_size_t
     L.blip_sm_batched_workspace_size.argtypes = [ci, i64]
+    L.blip_qs_propose.restype = ci
+    L.blip_qs_propose.argtypes = [i64, vp, vp, vp, vp]
+    L.blip_qs_accept.restype = ci
+    L.blip_qs_accept.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, i64, vp, vp]
+    L.blip_qs_kinetic.restype = ci
+    L.blip_qs_kinetic.argtypes = [ci, ci, vp, vp, vp]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]

@@ -1,0 +1,127 @@
+"""Quasi-simultaneous Monte Carlo steps for many walkers, on the device.
+
+A walker is 2n electrons (n of each spin) in the potential-free synthetic
+system whose trial function is the Slater part of Eq. (6): one determinant of
+Eq. (5) per spin, over the table's L = n real orbitals, p = |Psi_D|^2.  One
+quasi-simultaneous step (Sec. IV.A; the sequence of Sec. II.B) runs as:
+
+  blip_qs_propose          trial = pos + eta for every electron
+  blip_eval (values)       psi_l at every trial position (the new rows)
+  blip_eval_ratio          each move's ratio against the old configuration
+  blip_qs_accept           uniform < ratio^2; accepted positions copied and
+                           listed per (walker, spin) in electron order
+  blip_sm_update_batched   the inverses brought up to date for those moves
+  blip_eval_ratio + blip_qs_kinetic   the local kinetic energy per walker,
+                           -1/2 sum_j lap_j Psi / Psi at the new positions
+
+Random numbers are the caller's (eta Gaussian, uniform in [0, 1)), so a step
+can be replayed against the FP64 oracle.  Everything above runs in this
+library's kernels on the caller's stream; PyTorch only holds the buffers.
+Setting up the first inverses from scratch (``Walkers(..., inv_t=None)``)
+uses torch.linalg.inv once: that is setup, not part of a step.
+
+Layout: pos [W, 2n, 3] float64 (electron g of walker w is spin g // n,
+index g % n); inverses [W, 2, n, n] float64, row j of [w, s] = column j of
+D_{w,s}^{-1} (the layout blip_eval_ratio and blip_sm_update read).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import blip as _b
+
+
+class Walkers:
+    def __init__(self, table: "_b.Table", pos: torch.Tensor, inv_t: torch.Tensor | None = None,
+                 stream=None):
+        if table.complex:
+            raise ValueError("the synthetic system uses real orbitals")
+        W, ne, three = pos.shape
+        n = table.norb
+        if three != 3 or ne != 2 * n or pos.dtype != torch.float64 or not pos.is_cuda:
+            raise ValueError(f"pos must be cuda float64 [W, 2n = {2 * n}, 3]")
+        self.t, self.W, self.n, self.stream = table, W, n, stream
+        dev = pos.device
+        self.pos = pos.contiguous()
+        npos = W * 2 * n
+        self.trial = torch.empty_like(self.pos)
+        self.val = torch.empty((npos, n), dtype=torch.float32, device=dev)
+        self.ratio = torch.empty(npos, dtype=torch.float64, device=dev)
+        self.rg = torch.empty((npos, 3), dtype=torch.float64, device=dev)
+        self.rl = torch.empty(npos, dtype=torch.float64, device=dev)
+        self.acc_cols = torch.zeros((2 * W, n), dtype=torch.int32, device=dev)
+        self.acc_count = torch.zeros(2 * W, dtype=torch.int32, device=dev)
+        self.seq = torch.empty((2 * W, n), dtype=torch.float64, device=dev)
+        self.e_kin = torch.empty(W, dtype=torch.float64, device=dev)
+        nbytes = _b.lib().blip_sm_batched_workspace_size(2 * W, n)
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        if inv_t is None:
+            self.t.eval(self.pos.view(npos, 3), grad=False, out=(self.val, None, None),
+                        stream=stream)
+            D = self.val.view(2 * W, n, n).double()
+            inv_t = torch.linalg.inv(D).transpose(1, 2)
+        if tuple(inv_t.shape) != (W, 2, n, n) and tuple(inv_t.shape) != (2 * W, n, n):
+            raise ValueError(f"inv_t must be [W, 2, n, n] (got {tuple(inv_t.shape)})")
+        self.inv = inv_t.reshape(2 * W, n, n).to(torch.float64).contiguous()
+
+    def _call(self, rc):
+        _b.check(rc)
+
+    def step(self, eta: torch.Tensor, uniform: torch.Tensor, energy: bool = True,
+             j0: int = 0, j1: int | None = None):
+        """One quasi-simultaneous step with the given random numbers
+        (eta [W, 2n, 3] bohr, uniform [W, 2n]; cuda float64).  Candidates of
+        each (walker, spin) are its electrons j in [j0, j1) (default all).
+        Returns (accepted counts [2W] int32, e_kin [W] or None), device
+        tensors owned by this object."""
+        W, n, s = self.W, self.n, self.stream
+        npos = W * 2 * n
+        L = _b.lib()
+        eta = eta.contiguous()
+        uniform = uniform.contiguous()
+        self._call(L.blip_qs_propose(npos, _b._ptr(self.pos), _b._ptr(eta), _b._ptr(self.trial),
+                                     _b._stream_ptr(s)))
+        tr = self.trial.view(npos, 3)
+        self.t.eval(tr, grad=False, out=(self.val, None, None), stream=s)
+        rows = self.inv.view(npos, n)
+        self.t.ratio(tr, rows, grad=False, out=(self.ratio, None, None), stream=s)
+        self._call(L.blip_qs_accept(2 * W, n, j0, n if j1 is None else j1, _b._ptr(self.ratio),
+                                    _b._ptr(uniform), _b._ptr(self.trial), _b._ptr(self.pos),
+                                    _b._ptr(self.acc_cols), n, _b._ptr(self.acc_count),
+                                    _b._stream_ptr(s)))
+        _b.sm_update_batched(self.inv, self.val.view(2 * W, n, n), self.acc_cols,
+                             self.acc_count, n, ratios=self.seq, workspace=self.ws, stream=s)
+        e = None
+        if energy:
+            e = self.kinetic()
+        return self.acc_count, e
+
+    def kinetic(self):
+        """Local kinetic energy of every walker at its current positions."""
+        W, n, s = self.W, self.n, self.stream
+        npos = W * 2 * n
+        self.t.ratio(self.pos.view(npos, 3), self.inv.view(npos, n), grad=True,
+                     out=(self.ratio, self.rg, self.rl), stream=s)
+        self._call(_b.lib().blip_qs_kinetic(W, 2 * n, _b._ptr(self.rl), _b._ptr(self.e_kin),
+                                           _b._stream_ptr(s)))
+        return self.e_kin
+
+    def pbp_sweep(self, eta: torch.Tensor, uniform: torch.Tensor, energy: bool = True):
+        """The configuration-by-configuration comparison: electron g of every
+        walker moves alone, g = 0 .. 2n-1, each judged against the state that
+        holds the earlier decisions (one masked step per electron; for
+        comparisons on small systems, not a fast path)."""
+        W, n = self.W, self.n
+        inf = torch.full_like(uniform, float("inf"))
+        zero = torch.zeros_like(eta)
+        for g in range(2 * n):
+            e_g = zero.clone()
+            e_g[:, g] = eta[:, g]
+            u_g = inf.clone()
+            u_g[:, g] = uniform[:, g]
+            j = g % n
+            self.step(e_g, u_g, energy=False, j0=j, j1=j + 1)
+        return self.kinetic() if energy else None

@@ -168,3 +168,31 @@ def test_sm_update_batched_argument_errors(blip):
     assert call(w=ctypes.c_void_p(0x10004)) == -5
     assert call(nmat=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
     assert call(max_k=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
+
+
+def test_qs_helpers_argument_errors(blip):
+    """blip_qs_propose / blip_qs_accept / blip_qs_kinetic reject bad sizes,
+    ranges and alignment on the host (fake pointers, never dereferenced)."""
+    L = blip.lib()
+    dev = ctypes.c_void_p(0x10000)
+    odd = ctypes.c_void_p(0x10004)
+    assert L.blip_qs_propose(-1, dev, dev, dev, None) == -1
+    assert L.blip_qs_propose(0, None, None, None, None) == 0
+    assert L.blip_qs_propose(4, None, dev, dev, None) == -1
+    assert L.blip_qs_propose(4, odd, dev, dev, None) == -5
+
+    def acc(nmat=2, n=8, j0=0, j1=8, ld=8, ratio=dev, cols=dev):
+        return L.blip_qs_accept(nmat, n, j0, j1, ratio, dev, dev, dev, cols, ld, dev, None)
+
+    assert acc(nmat=-1) == -1 and acc(nmat=70000) == -1
+    assert acc(n=0) == -1
+    assert acc(j0=-1) == -1 and acc(j0=5, j1=4) == -1 and acc(j1=9) == -1
+    assert acc(ld=7) == -1
+    assert acc(ratio=None) == -1
+    assert acc(ratio=odd) == -5
+    assert acc(cols=ctypes.c_void_p(0x10002)) == -5
+    assert acc(nmat=0) == 0
+    assert L.blip_qs_kinetic(-1, 8, dev, dev, None) == -1
+    assert L.blip_qs_kinetic(2, 0, dev, dev, None) == -1
+    assert L.blip_qs_kinetic(2, 8, odd, dev, None) == -5
+    assert L.blip_qs_kinetic(0, 8, None, None, None) == 0

@@ -1,0 +1,109 @@
+"""Quasi-simultaneous and configuration-by-configuration Monte Carlo steps on
+the GPU (paper_1204_1121_amd/vmc.py) against the FP64 oracle (oracle/vmc.py)
+with the same random numbers.
+
+Both sides take the same accept decisions unless a uniform lies within
+rounding of ratio^2; the test asserts that no decision is that close, so the
+positions must then agree bit for bit (the trial positions are the same FP64
+sums).  The GPU's orbital rows are FP32, so its inverses and energies differ
+from the oracle's by the FP32 rounding of the rows amplified by the
+condition number: bar 64 * cond * 2^-24 relative to max |B| (and for the
+kinetic energy, relative to the sum of |lap ratio| terms)."""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import vmc as ovmc
+from tests.gpu_util import say, to_np
+
+pytestmark = pytest.mark.gpu
+
+A = np.array([[6.0, 0.3, 0.0], [0.2, 5.0, 0.4], [0.0, -0.3, 5.5]])
+NG = (12, 11, 10)
+L = 8
+W = 3
+TIE = 1e-5
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import vmc
+    rng = np.random.default_rng(zlib.crc32(b"gpu-vmc"))
+    coef = rng.uniform(-1, 1, NG + (L,)).astype(np.float32)
+    t = blip.Table(A, NG, coef, "f32")
+    pos = rng.uniform(0, 1, (W, 2 * L, 3)) @ A
+    inv = np.stack([np.stack([np.linalg.inv(D).T for D in ovmc.slater_matrices(A, NG, coef, p)])
+                    for p in pos])
+    yield blip, vmc, t, coef, pos, inv, rng
+    t.free()
+
+
+def cond_bar(coef, pos_w):
+    D = ovmc.slater_matrices(A, NG, coef, pos_w)
+    return 64 * max(np.linalg.cond(D[0]), np.linalg.cond(D[1])) * 2.0 ** -24
+
+
+def lap_scale(coef, pos_w, inv_w):
+    o = ovmc.evaluate(A, NG, coef, pos_w, want=("val", "grad", "lap"))
+    return 0.5 * (np.abs(o["lap"][:L] * inv_w[0]).sum() + np.abs(o["lap"][L:] * inv_w[1]).sum())
+
+
+def test_qs_steps_match_oracle(setup):
+    blip, vmc, t, coef, pos, inv, rng = setup
+    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(inv.copy()).cuda())
+    cur_pos, cur_inv = pos.copy(), inv.copy()
+    for step in range(3):
+        eta = rng.normal(0, 0.5, pos.shape)
+        uni = rng.uniform(0, 1, (W, 2 * L))
+        cnt, e = wk.step(torch.from_numpy(eta).cuda(), torch.from_numpy(uni).cuda())
+        torch.cuda.synchronize()
+        g_pos, g_inv, g_e = to_np(wk.pos), to_np(wk.inv).reshape(W, 2, L, L), to_np(e)
+        g_cnt = to_np(cnt).reshape(W, 2)
+        for w in range(W):
+            npos, ninv, acc, ratio, _, ek = ovmc.qs_step(A, NG, coef, cur_pos[w], cur_inv[w],
+                                                          eta[w], uni[w])
+            assert np.min(np.abs(uni[w] - ratio * ratio)) > TIE, "a decision is within rounding"
+            assert [acc[:L].sum(), acc[L:].sum()] == list(g_cnt[w]), (step, w)
+            np.testing.assert_array_equal(g_pos[w], npos, err_msg=f"step {step} walker {w}")
+            bar = cond_bar(coef, npos)
+            eb = np.abs(g_inv[w] - ninv).max() / np.abs(ninv).max()
+            ee = abs(g_e[w] - ek) / lap_scale(coef, npos, ninv)
+            say(f"step {step} walker {w}: accepted {g_cnt[w].tolist()}, inverse err {eb:.1e}, "
+                f"energy err {ee:.1e} (bar {bar:.1e})")
+            assert eb <= bar and ee <= bar
+            cur_pos[w], cur_inv[w] = npos, ninv
+
+
+def test_pbp_sweep_matches_oracle(setup):
+    blip, vmc, t, coef, pos, inv, rng = setup
+    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(inv.copy()).cuda())
+    eta = rng.normal(0, 0.5, pos.shape)
+    uni = rng.uniform(0, 1, (W, 2 * L))
+    e = wk.pbp_sweep(torch.from_numpy(eta).cuda(), torch.from_numpy(uni).cuda())
+    torch.cuda.synchronize()
+    g_pos, g_inv, g_e = to_np(wk.pos), to_np(wk.inv).reshape(W, 2, L, L), to_np(e)
+    for w in range(W):
+        npos, ninv, acc, ek = ovmc.pbp_sweep(A, NG, coef, pos[w], inv[w], eta[w], uni[w])
+        np.testing.assert_array_equal(g_pos[w], npos, err_msg=f"walker {w}")
+        bar = cond_bar(coef, npos)
+        eb = np.abs(g_inv[w] - ninv).max() / np.abs(ninv).max()
+        ee = abs(g_e[w] - ek) / lap_scale(coef, npos, ninv)
+        say(f"PbP walker {w}: accepted {int(acc.sum())} of {2 * L}, inverse err {eb:.1e}, "
+            f"energy err {ee:.1e} (bar {bar:.1e})")
+        assert eb <= bar and ee <= bar
+
+
+def test_setup_inverse_and_kinetic_of_fresh_walkers(setup):
+    """Walkers built without inverses invert their Slater matrices once; the
+    kinetic energy at the start matches the oracle's."""
+    blip, vmc, t, coef, pos, inv, rng = setup
+    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda())
+    e = to_np(wk.kinetic())
+    for w in range(W):
+        ek = ovmc.local_kinetic(A, NG, coef, pos[w], inv[w])
+        assert abs(e[w] - ek) <= cond_bar(coef, pos[w]) * lap_scale(coef, pos[w], inv[w])
