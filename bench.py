@@ -438,6 +438,140 @@ def bench_precision(args, real_coef, real_spec, cache, leg=None):
     return out
 
 
+def bench_vmc(args, table, spec):
+    """Quasi-simultaneous Monte Carlo steps on the device.
+
+    Throughput: 16 walkers of the TiO2 system (2 x 768 electrons each, the
+    768-orbital table), one full step each time (trial moves, values and
+    ratios at the trial positions, accept/reject, batched inverse updates,
+    local kinetic energy), with the time of each phase.
+
+    Statistics (the paper's comparison of quasi-simultaneous and
+    configuration-by-configuration updating, Table energy_eval, on a
+    synthetic system): 64 walkers of 2 x 8 electrons on a small table,
+    both chains from the same start, acceptance and mean local kinetic energy
+    with the standard error over the independent walkers."""
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import vmc
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    res = {}
+    # -- throughput on the TiO2 system
+    W, n = 16, spec.norb
+    g = torch.Generator(device="cuda").manual_seed(wl.SEED_BASE + 11)
+    lat = torch.from_numpy(spec.lattice).cuda()
+    pos = torch.rand((W, 2 * n, 3), dtype=torch.float64, device="cuda", generator=g) @ lat
+    wk = vmc.Walkers(table, pos, stream=stream)
+    sigma = 0.35
+    etas = [sigma * torch.randn((W, 2 * n, 3), dtype=torch.float64, device="cuda", generator=g)
+            for _ in range(4)]
+    unis = [torch.rand((W, 2 * n), dtype=torch.float64, device="cuda", generator=g) for _ in range(4)]
+    for i in range(3):
+        wk.step(etas[i % 4], unis[i % 4])
+    torch.cuda.synchronize()
+    steps = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for i in range(steps):
+        wk.step(etas[i % 4], unis[i % 4])
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_step = ev[0].elapsed_time(ev[1]) * 1e-3 / steps
+    acc = float(wk.acc_count.sum().item()) / (W * 2 * n)
+    # phases, each timed alone over the same step inputs
+    npos = W * 2 * n
+    tr = wk.trial.view(npos, 3)
+    phases = {
+        "values at trial positions": lambda: table.eval(tr, grad=False, out=(wk.val, None, None),
+                                                        stream=stream),
+        "ratios against the old inverses": lambda: table.ratio(tr, wk.inv.view(npos, n), grad=False,
+                                                               out=(wk.ratio, None, None),
+                                                               stream=stream),
+        "local kinetic energy": wk.kinetic,
+    }
+    ph = {}
+    for name, fn in phases.items():
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ph[name] = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+    ph["accept + inverse updates + propose (rest of the step)"] = t_step * 1e6 - sum(ph.values())
+    res["throughput"] = {"walkers": W, "electrons_per_walker": 2 * n, "orbitals": n,
+                         "us_per_step": t_step * 1e6, "walker_steps_per_s": W / t_step,
+                         "electron_moves_per_s": W * 2 * n / t_step, "acceptance": acc,
+                         "sigma_bohr": sigma, "phases_us": ph}
+    del wk
+    log(f"vmc: {t_step * 1e6:.0f} us per quasi-simultaneous step of {W} walkers x {2 * n} "
+        f"electrons ({W / t_step:.0f} walker-steps/s, acceptance {acc:.2f})")
+
+    # -- statistics: quasi-simultaneous against configuration-by-configuration
+    A = np.array([[6.0, 0.3, 0.0], [0.2, 5.0, 0.4], [0.0, -0.3, 5.5]])
+    ng, Ls, Ws = (12, 11, 10), 8, 64
+    rng = np.random.default_rng(wl.SEED_BASE + 12)
+    coef = rng.uniform(-1, 1, ng + (Ls,)).astype(np.float32)
+    ts = blip.Table(A, ng, coef, "f32")
+    start = torch.from_numpy(rng.uniform(0, 1, (Ws, 2 * Ls, 3)) @ A).cuda()
+    chains = {"quasi_simultaneous": vmc.Walkers(ts, start.clone(), stream=stream),
+              "configuration_by_configuration": vmc.Walkers(ts, start.clone(), stream=stream)}
+    nequil, nsample, sig = 200, 1000, 0.3
+    stats = {}
+    for name, wk in chains.items():
+        gs = torch.Generator(device="cuda").manual_seed(wl.SEED_BASE + 13)   # same draws
+        esum = torch.zeros(Ws, dtype=torch.float64, device="cuda")
+        emax = torch.zeros((), dtype=torch.float64, device="cuda")
+        acc_n = torch.zeros((), dtype=torch.float64, device="cuda")
+        seq_min = torch.full((), float("inf"), dtype=torch.float64, device="cuda")
+        lanes = torch.arange(Ls, device="cuda")[None, :]
+        t0 = time.perf_counter()
+        for it in range(nequil + nsample):
+            eta = sig * torch.randn((Ws, 2 * Ls, 3), dtype=torch.float64, device="cuda",
+                                    generator=gs)
+            uni = torch.rand((Ws, 2 * Ls), dtype=torch.float64, device="cuda", generator=gs)
+            if name == "quasi_simultaneous":
+                cnt, e = wk.step(eta, uni)
+                seq = torch.where(lanes < wk.acc_count[:, None], wk.seq.abs(),
+                                  torch.full_like(wk.seq, float("inf")))
+                seq_min = torch.minimum(seq_min, seq.min())
+            else:
+                before = wk.pos.clone()
+                e = wk.pbp_sweep(eta, uni)
+                cnt = (wk.pos != before).any(dim=2).sum()
+            if it >= nequil:
+                esum += e
+                emax = torch.maximum(emax, e.abs().max())
+                acc_n += cnt.sum()
+        torch.cuda.synchronize()
+        ew = (esum / nsample).cpu().numpy()
+        stats[name] = {"mean_kinetic_hartree": float(ew.mean()),
+                       "stderr": float(ew.std(ddof=1) / np.sqrt(Ws)),
+                       "median_walker_mean": float(np.median(ew)),
+                       "max_abs_local_energy": float(emax.item()),
+                       "acceptance": float(acc_n.item()) / (nsample * Ws * 2 * Ls),
+                       "seconds": time.perf_counter() - t0}
+        if name == "quasi_simultaneous":
+            stats[name]["min_sequential_ratio"] = float(seq_min.item())
+    q, c = stats["quasi_simultaneous"], stats["configuration_by_configuration"]
+    diff = q["mean_kinetic_hartree"] - c["mean_kinetic_hartree"]
+    err = float(np.hypot(q["stderr"], c["stderr"]))
+    stats["difference_in_stderr"] = diff / err
+    stats["setup"] = (f"{Ws} walkers x {2 * Ls} electrons, {Ls} orbitals on a {ng} grid, "
+                      f"sigma {sig} bohr, {nequil} equilibration + {nsample} sampled steps, the "
+                      "same random draws for both chains; stderr over walker means")
+    res["statistics"] = stats
+    log(f"vmc statistics: Q.S. E_kin {q['mean_kinetic_hartree']:.2f} +- {q['stderr']:.2f} "
+        f"(median walker {q['median_walker_mean']:.2f}, max |E_L| {q['max_abs_local_energy']:.3g}, "
+        f"acceptance {q['acceptance']:.3f}); PbP {c['mean_kinetic_hartree']:.2f} +- "
+        f"{c['stderr']:.2f} (median walker {c['median_walker_mean']:.2f}, max |E_L| "
+        f"{c['max_abs_local_energy']:.3g}, acceptance {c['acceptance']:.3f})")
+    ts.free()
+    return res
+
+
 PAPER_SYSTEMS = (  # (system, electrons N, orbitals L, the paper's GPU ms per step, CPU ms)
     ("Si 3x3x3", 216, 56, 0.17, 2.77),
     ("TiO2 3x3x3", 648, 168, 0.82, 20.21),
@@ -523,6 +657,8 @@ def main():
                     help="skip the storage-dtype / complex k-point section")
     ap.add_argument("--no-paper-sizes", action="store_true",
                     help="skip the values-only complex section at the paper's system sizes")
+    ap.add_argument("--no-vmc", action="store_true",
+                    help="skip the Monte Carlo step throughput and statistics section")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving rate point")
     ap.add_argument("--copy-probe", action="store_true",
@@ -691,6 +827,12 @@ def main():
                 cache.save(args.save_tuning)
         except Exception as e:
             result["precision"] = {"error": f"{type(e).__name__}: {e}"}
+
+    if not args.no_vmc:
+        try:
+            result["vmc"] = bench_vmc(args, table, spec)
+        except Exception as e:
+            result["vmc"] = {"error": f"{type(e).__name__}: {e}"}
 
     if not args.no_paper_sizes:
         try:
