@@ -483,11 +483,9 @@ def bench_vmc(args, table, spec):
     npos = W * 2 * n
     tr = wk.trial.view(npos, 3)
     phases = {
-        "values at trial positions": lambda: table.eval(tr, grad=False, out=(wk.val, None, None),
-                                                        stream=stream),
-        "ratios against the old inverses": lambda: table.ratio(tr, wk.inv.view(npos, n), grad=False,
-                                                               out=(wk.ratio, None, None),
-                                                               stream=stream),
+        "ratios and values at the trial positions (one pass)":
+            lambda: table.ratio_values(tr, wk.inv.view(npos, n), out=(wk.ratio, wk.val),
+                                       stream=stream),
         "local kinetic energy": wk.kinetic,
     }
     ph = {}

@@ -258,6 +258,18 @@ BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
                              void* stream);
 
 /*
+ * blip_eval_ratio_values -- the values-only blip_eval_ratio that also writes
+ * the orbital values, val [npos][L] float, exactly as blip_eval writes them:
+ * one pass gives a quasi-simultaneous step both its ratios and the new
+ * orbital rows that the inverse update (blip_sm_update*) needs for the
+ * accepted moves.  Same arguments and errors as blip_eval_ratio; val is
+ * required, 4-byte aligned.
+ */
+BLIP_API int blip_eval_ratio_values(blip_table t, const double* pos, int64_t npos,
+                                    const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
+                                    double* ratio, void* val, void* stream);
+
+/*
  * blip_eval_ratio_batched -- blip_eval_ratio for many walkers in one
  * persistent launch: positions concatenated and offsets as in
  * blip_eval_batched (only offsets[nw] is read, on the device), row_of[j]

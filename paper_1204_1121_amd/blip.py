@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.blip_get_shape.argtypes = [vp, ci, i64, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     L.blip_eval_ratio.restype = ci
     L.blip_eval_ratio.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+    L.blip_eval_ratio_values.restype = ci
+    L.blip_eval_ratio_values.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp]
     L.blip_eval_ratio_batched.restype = ci
     L.blip_eval_ratio_batched.argtypes = [vp, vp, vp, ci, i64, vp, i64, vp, vp, vp, vp, vp,
                                           ctypes.c_size_t, vp]
@@ -241,6 +243,22 @@ class Table:
                                     inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(g),
                                     _ptr(l), _stream_ptr(stream)))
         return r, g, l
+
+    def ratio_values(self, pos: torch.Tensor, inv_rows: torch.Tensor, row_of=None, out=None,
+                     stream=None):
+        """blip_eval_ratio_values: the ratios and, in the same pass, the orbital
+        values.  Returns (ratio [npos] float64, val [npos, L] float32)."""
+        if inv_rows.dtype != torch.float64 or inv_rows.dim() != 2 or inv_rows.stride(1) != 1:
+            raise ValueError("inv_rows must be a float64 CUDA matrix with unit column stride")
+        npos = pos.shape[0]
+        if out is None:
+            out = (torch.empty(npos, dtype=torch.float64, device=pos.device),
+                   torch.empty((npos, self.norb), dtype=torch.float32, device=pos.device))
+        r, v = out
+        check(lib().blip_eval_ratio_values(self.handle, _ptr(pos), npos, _ptr(inv_rows),
+                                           inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(v),
+                                           _stream_ptr(stream)))
+        return r, v
 
     def ratio_batched(self, pos, offsets, inv_rows, row_of=None, grad: bool = True, out=None,
                       workspace=None, capacity: int | None = None, stream=None):

@@ -718,6 +718,11 @@ tiled_kernel(const KArgs a)
 #pragma unroll
                     for (int q = 0; q < NR; ++q) part[p][ch][q] = dot[q];
                 }
+                // optionally the values too: the new orbital rows that the
+                // inverse update after the accept/reject step needs
+                if (a.val != nullptr && lane_ok)
+                    store_elems<OE>(static_cast<ACC*>(a.val) + jo * W + e0, res[0], e0, W,
+                                    a.vec_store != 0);
                 continue;   // nothing else is stored for this item
             }
             if (lane_ok) {

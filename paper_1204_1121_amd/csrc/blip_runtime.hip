@@ -515,6 +515,23 @@ BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
                         nullptr, nullptr, nullptr, 0, false, static_cast<hipStream_t>(stream), &ra);
 }
 
+BLIP_API int blip_eval_ratio_values(blip_table t, const double* pos, int64_t npos,
+                                    const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
+                                    double* ratio, void* val, void* stream)
+{
+    int rc = check_ratio_args(t, npos, pos, inv_rows, inv_ld, row_of, ratio, nullptr, nullptr);
+    if (rc != BLIP_OK || npos == 0) return rc;
+    if (val == nullptr) return fail(BLIP_E_ARG, "val is required");
+    if ((reinterpret_cast<uintptr_t>(val) & 3u) != 0)
+        return fail(BLIP_E_ALIGN, "val needs 4-byte alignment");
+    int P = 0, OE = 0;
+    rc = ratio_shape(t, MODE_BLOCK, npos, P, OE);
+    if (rc != BLIP_OK) return rc;
+    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, nullptr, nullptr};
+    return launch_tiled(t, pos, npos, val, nullptr, nullptr, KIND_TILED, P, OE, nullptr, nullptr,
+                        nullptr, nullptr, 0, false, static_cast<hipStream_t>(stream), &ra);
+}
+
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage, int64_t* row_bytes,
                              int64_t* device_bytes)
 {

@@ -6,8 +6,9 @@ Eq. (5) per spin, over the table's L = n real orbitals, p = |Psi_D|^2.  One
 quasi-simultaneous step (Sec. IV.A; the sequence of Sec. II.B) runs as:
 
   blip_qs_propose          trial = pos + eta for every electron
-  blip_eval (values)       psi_l at every trial position (the new rows)
-  blip_eval_ratio          each move's ratio against the old configuration
+  blip_eval_ratio_values   in one pass: each move's ratio against the old
+                           configuration and psi_l at every trial position
+                           (the new rows)
   blip_qs_accept           uniform < ratio^2; accepted positions copied and
                            listed per (walker, spin) in electron order
   blip_sm_update_batched   the inverses brought up to date for those moves
@@ -85,9 +86,7 @@ class Walkers:
         self._call(L.blip_qs_propose(npos, _b._ptr(self.pos), _b._ptr(eta), _b._ptr(self.trial),
                                      _b._stream_ptr(s)))
         tr = self.trial.view(npos, 3)
-        self.t.eval(tr, grad=False, out=(self.val, None, None), stream=s)
-        rows = self.inv.view(npos, n)
-        self.t.ratio(tr, rows, grad=False, out=(self.ratio, None, None), stream=s)
+        self.t.ratio_values(tr, self.inv.view(npos, n), out=(self.ratio, self.val), stream=s)
         self._call(L.blip_qs_accept(2 * W, n, j0, n if j1 is None else j1, _b._ptr(self.ratio),
                                     _b._ptr(uniform), _b._ptr(self.trial), _b._ptr(self.pos),
                                     _b._ptr(self.acc_cols), n, _b._ptr(self.acc_count),

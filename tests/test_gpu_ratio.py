@@ -151,3 +151,33 @@ def test_batched_ratio_equals_per_walker(blip):
     check_ratio({"ratio": to_np(rb), "grad": to_np(gb), "lap": to_np(lb)}, ref, vals,
                 np.concatenate(invs), np.concatenate(rows), 1e-5, "batched vs oracle")
     t.free()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_ratio_values_one_pass(blip, storage):
+    """blip_eval_ratio_values: the ratios equal blip_eval_ratio's and the
+    values equal values-only blip_eval's, bit for bit, with aligned outputs
+    (whole-vector stores) and with a value array offset by one float."""
+    rng = np.random.default_rng(11)
+    n = (9, 10, 11)
+    L = 64
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    R, inv_rows, moves = setup(SKEW, n, c, L, 2)
+    t = blip.Table(SKEW, n, c, storage)
+    p = torch.from_numpy(moves).cuda()
+    inv = torch.from_numpy(inv_rows).cuda()
+    want_r = to_np(t.ratio(p, inv, grad=False)[0])
+    want_v = to_np(t.eval(p, grad=False)[0])
+    r, v = t.ratio_values(p, inv)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(r), want_r)
+    np.testing.assert_array_equal(to_np(v), want_v)
+    buf = torch.full((L * L + 1,), 7.0, dtype=torch.float32, device="cuda")
+    v_off = buf[1:].view(L, L)                       # 4-byte aligned, not 16
+    r2 = torch.empty(L, dtype=torch.float64, device="cuda")
+    t.ratio_values(p, inv, out=(r2, v_off))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(r2), want_r)
+    np.testing.assert_array_equal(to_np(v_off), want_v)
+    assert to_np(buf)[0] == 7.0
+    t.free()
