@@ -239,8 +239,9 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 // into bounds and unwanted values replaced by zero afterwards, so each group
 // of loads is issued back to back and waited for once.  Only the uniform
 // tests kp > 0 and kn > 0 guard buffers that may be absent.
+//
 template <bool BATCHED, int ROWS>
-__global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
+__device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
     constexpr int RPT = ROWS / 2;          // rows per thread in the update
     constexpr int VPT = ROWS / 8;          // entries of V (and Y) per thread
@@ -452,10 +453,25 @@ __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
     }
 }
 
+__global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
+{
+    sm_chunk_body<false, kSmRows>(a);
+}
+
+// The 16-row tile takes 170 registers (two waves per SIMD); asking for three
+// waves spills two of them to scratch, and the third wave hides enough load
+// latency to make the batched step about 17% faster per matrix.  The 8-row
+// tile already fits three waves and is left to the compiler's choice.
+__global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void sm_chunk_batched_kernel(SmArgs a)
+{
+    sm_chunk_body<true, kSmRowsBatched>(a);
+}
+
 hipError_t sm_launch(const SmArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)((a.n + kSmRows - 1) / kSmRows), (unsigned)a.nct);
-    hipLaunchKernelGGL((sm_chunk_kernel<false, kSmRows>), grid, dim3(kSmThreads), 0, s, a);
+    hipLaunchKernelGGL(sm_chunk_kernel, grid, dim3(kSmThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -634,9 +650,9 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         }
         a.Pn = V[c & 1];
         a.Rn = R[c & 1];
-        hipLaunchKernelGGL((sm_chunk_kernel<true, kSmRowsBatched>), grid, dim3(kSmThreads), 0, s, a);
+        hipLaunchKernelGGL(sm_chunk_batched_kernel, grid, dim3(kSmThreads), 0, s, a);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail_hip(e, "sm_chunk_kernel launch");
+        if (e != hipSuccess) return fail_hip(e, "sm_chunk_batched_kernel launch");
     }
     return BLIP_OK;
 }
