@@ -577,7 +577,51 @@ PAPER_SYSTEMS = (  # (system, electrons N, orbitals L, the paper's GPU ms per st
 )
 
 
-def bench_paper_sizes(args, leg=None):
+# The paper's GPU times per Monte Carlo step for its three mappings (Table
+# kernel_time0, GTX 480, kernel plus PCIe), quoted for N = 216 and 1,536.
+PAPER_MAPPING_MS = {
+    216: {"(1)": 6.76, "(2)": 0.43, "(3)": 0.17},
+    1536: {"(1)": 68.03, "(2)": 17.83, "(3)": 3.26},
+}
+MAPPINGS = (  # (reported name, kernel, short label)
+    ("(3) quasi-simultaneous, coalesced: tuned tiled kernel", "auto", "(3) tiled"),
+    ("(3) quasi-simultaneous, coalesced: plain kernel", "plain", "(3) plain"),
+    ("(2) quasi-simultaneous, non-coalesced: site-parallel kernel", "site", "(2)"),
+    ("(1) particle-by-particle: N site-parallel launches of one position", "pbp", "(1)"),
+)
+
+
+def time_per_position_launches(table, pos, out, reps=3):
+    """GPU seconds for one pass of the particle-by-particle form over a
+    block: one site-parallel launch per position, captured once in a graph
+    so that the host's enqueue rate does not set the time.  The replayed
+    rows must equal one site-parallel launch over the whole block."""
+    import torch
+    want = table.eval(pos, grad=False, kernel="site")[0]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        calls = [table.bind(pos[j:j + 1], (out[0][j:j + 1], None, None), kernel="site")
+                 for j in range(pos.shape[0])]
+        for call in calls:
+            call()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    if not torch.equal(out[0], want):
+        raise RuntimeError("per-position launches differ from the block launch")
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def bench_paper_sizes(args, cache, leg=None):
     """The paper's own workload shape (Table system_size): complex orbital
     values only, one evaluation of all L orbitals at the N moved electrons of
     a quasi-simultaneous step, for its three (N, L).  Synthetic complex64
@@ -597,11 +641,24 @@ def bench_paper_sizes(args, leg=None):
         t = blip.Table(spec.lattice, spec.n, coef, "c64", kvec=spec.kvec)
         blocks = [torch.from_numpy(wl.move_block(spec, N, block=b)).cuda() for b in range(NROT)]
         o = t.alloc_outputs(N, grad=False)
-        calls = {id(b): t.bind(b, o) for b in blocks}
-        _, tk = time_region(lambda b: calls[id(b)](), blocks, 200, 20, stream)
+        if args.retune or not cache.apply(t, N, values_only=True):
+            best, _ = t.autotune(torch.cat(blocks).contiguous(), o, rotate=NROT)
+            cache.put(t, N, False, best, note=f"blip_autotune rotate={NROT}, values only",
+                      values_only=True)
+        times = {}
+        for key, kern, _ in MAPPINGS:
+            if kern == "pbp":
+                times[key] = time_per_position_launches(t, blocks[0], o)
+                continue
+            calls = {id(b): t.bind(b, o, kernel=kern) for b in blocks}
+            steps, warm = (200, 20) if kern != "site" else (20, 3)
+            _, times[key] = time_region(lambda b: calls[id(b)](), blocks, steps, warm, stream)
+        tk = times[MAPPINGS[0][0]]
         row = {"system": name, "N": N, "L": L, "kernel_us": tk * 1e6,
                "complex_values_per_s": N * L / tk,
+               "mappings_us": {k: v * 1e6 for k, v in times.items()},
                "paper_gtx480_ms_kernel_plus_pcie": paper_gpu_ms,
+               "paper_gtx480_ms_by_mapping": PAPER_MAPPING_MS.get(N),
                "paper_cpu_1core_ms": paper_cpu_ms}
         msg = ""
         if leg is not None:
@@ -609,9 +666,12 @@ def bench_paper_sizes(args, leg=None):
             dt = leg.time_values(spec, coef, pos0, nthreads=1)
             row["oracle_1core_ms"] = dt * 1e3
             row["speedup_vs_oracle_1core"] = dt / tk
+            row["acceleration_vs_oracle_1core"] = {k: dt / v for k, v in times.items()}
             msg = f", FP64 oracle on one core {dt * 1e3:.1f} ms ({dt / tk:.0f}x)"
         rows.append(row)
-        log(f"paper size {name} (N={N}, L={L}, complex, values only): {tk * 1e6:.1f} us{msg}")
+        log(f"paper size {name} (N={N}, L={L}, complex, values only): {tk * 1e6:.1f} us{msg}; "
+            "mappings " + ", ".join(f"{short} {times[key] * 1e6:.1f} us"
+                                    for key, _, short in MAPPINGS))
         t.free()
         del coef
     return rows
@@ -834,7 +894,9 @@ def main():
 
     if not args.no_paper_sizes:
         try:
-            result["paper_sizes"] = bench_paper_sizes(args, leg)
+            result["paper_sizes"] = bench_paper_sizes(args, cache, leg)
+            if args.save_tuning:
+                cache.save(args.save_tuning)
         except Exception as e:
             result["paper_sizes"] = {"error": f"{type(e).__name__}: {e}"}
 

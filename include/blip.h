@@ -78,9 +78,16 @@ typedef enum {
                                mapping (Sec. IV.B) written for wave64         */
     BLIP_KERNEL_TILED = 2,  /* P positions per workgroup, separable 1-D weights,
                                o orbitals per lane with wide loads             */
-    BLIP_KERNEL_F64ACC = 3  /* tiled kernel with FP64 weights, accumulation and
+    BLIP_KERNEL_F64ACC = 3, /* tiled kernel with FP64 weights, accumulation and
                                outputs (debug; real FP32 tables only): val, grad
                                and lap are double arrays of the same shapes    */
+    BLIP_KERNEL_SITE = 4    /* one wavefront per (position, orbital), one lane
+                               per stencil site, the 64 products summed across
+                               the wavefront: the paper's non-coalesced
+                               comparison mapping (Sec. IV.C, implementation
+                               (2)); called with npos = 1 per electron it is
+                               implementation (1).  For measurement: every
+                               load is uncoalesced by design                   */
 } blip_kernel;
 
 typedef struct {
@@ -143,7 +150,8 @@ BLIP_API int blip_eval(blip_table t, const double* pos, int64_t npos,
  * BLIP_E_DTYPE for BLIP_KERNEL_F64ACC on anything but BLIP_F32.
  * Every kernel and every (P, o) computes each output with the same sequence
  * of operations, so results agree bit for bit across tilings
- * (BLIP_KERNEL_PLAIN and BLIP_KERNEL_F64ACC round differently).
+ * (BLIP_KERNEL_PLAIN, BLIP_KERNEL_SITE and BLIP_KERNEL_F64ACC round
+ * differently).  tile_pos and vec are ignored by the plain and site kernels.
  */
 BLIP_API int blip_eval_ex(blip_table t, const double* pos, int64_t npos,
                           void* val, void* grad, void* lap,
@@ -203,15 +211,18 @@ BLIP_API int blip_plan_free(blip_plan p);
  * rotate, so that a launch does not find its rows left in the caches by the
  * previous one; otherwise (rotate must be 1) it tunes blip_eval_batched with
  * capacity npos (P in {8,16,32,64}).  o runs over
- * {1,2,4} (FP32 storage) or {2,4,8} (16-bit storage).  Synchronous: it
- * synchronises the stream after each timed launch.  The outputs are
+ * {1,2,4} (FP32 storage) or {2,4,8} (16-bit storage).  Each shape is timed
+ * as bursts of max(8, rotate) back-to-back launches (one untimed burst, then
+ * five timed), the figure being the median over bursts of the mean time per
+ * launch: the rate of a stream of steps, not the latency of one launch.
+ * Synchronous: it synchronises the stream after each burst.  The outputs are
  * overwritten.  results (may be NULL) receives up to max_results timings;
  * best receives the winner.
  */
 typedef struct {
     int tile_pos;   /* P */
     int vec;        /* o */
-    double us;      /* median launch time, microseconds */
+    double us;      /* per-launch time, microseconds (median over bursts) */
 } blip_tune_result;
 BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offsets, int nw,
                            int64_t npos, int rotate, void* val, void* grad, void* lap,

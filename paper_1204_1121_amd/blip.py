@@ -24,7 +24,7 @@ STATUS = {0: "BLIP_OK", -1: "BLIP_E_ARG", -2: "BLIP_E_OOM", -3: "BLIP_E_HIP",
           -4: "BLIP_E_DTYPE", -5: "BLIP_E_ALIGN", -6: "BLIP_E_STATE",
           -7: "BLIP_E_NODEV"}
 STORAGE = {"f32": 0, "bf16": 1, "f16": 2, "c64": 3, "cbf16": 4, "cf16": 5}
-KERNEL = {"auto": 0, "plain": 1, "tiled": 2, "f64acc": 3}
+KERNEL = {"auto": 0, "plain": 1, "tiled": 2, "f64acc": 3, "site": 4}
 
 
 class BlipError(RuntimeError):
@@ -204,15 +204,23 @@ class Table:
                                      ctypes.byref(o), sp))
         return val, g, lap
 
-    def bind(self, pos: torch.Tensor, out, stream=None):
-        """A zero-argument callable that runs ``blip_eval`` on fixed buffers
-        with the ctypes arguments built once (low host overhead per call)."""
+    def bind(self, pos: torch.Tensor, out, stream=None, kernel: str = "auto",
+             tile_pos: int = 0, vec: int = 0):
+        """A zero-argument callable that runs ``blip_eval`` (``blip_eval_ex``
+        for an explicit kernel or shape) on fixed buffers with the ctypes
+        arguments built once (low host overhead per call)."""
         if pos.dtype != torch.float64 or not pos.is_cuda or not pos.is_contiguous():
             raise ValueError("pos must be a contiguous float64 CUDA tensor [npos, 3]")
         val, g, lap = out
-        fn = lib().blip_eval
         args = (self.handle, _ptr(pos), ctypes.c_int64(pos.shape[0]), _ptr(val), _ptr(g),
-                _ptr(lap), _stream_ptr(stream))
+                _ptr(lap))
+        if kernel == "auto" and tile_pos == 0 and vec == 0:
+            fn = lib().blip_eval
+            args = args + (_stream_ptr(stream),)
+        else:
+            fn = lib().blip_eval_ex
+            opts = EvalOpts(KERNEL[kernel], int(tile_pos), int(vec))
+            args = args + (ctypes.byref(opts), _stream_ptr(stream))
         err = lib().blip_last_error
 
         def call():

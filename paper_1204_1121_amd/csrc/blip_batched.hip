@@ -290,6 +290,7 @@ struct blip_plan_s {
 
 using namespace blip;
 
+static constexpr int kTuneSamples = 5;   // timed bursts per candidate shape (median kept)
 static constexpr uint32_t kPlanMagic = 0xB11F91A4u;
 
 extern "C" {
@@ -434,24 +435,30 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
     for (int P : Ps) {
         for (int OE : Os) {
             if (!valid_oe(t, OE)) continue;
+            // One warm-up burst, then kTuneSamples timed bursts of
+            // back-to-back launches: the per-launch mean of a burst is what a
+            // stream of steps sees (an isolated launch would mostly time the
+            // launch latency of a small kernel).  Blocks rotate so a launch
+            // does not find its rows left in the caches by the launch before,
+            // as in a running simulation.
             std::vector<float> ts;
-            const int iters = 2 + std::max(7, rotate);
-            for (int it = 0; it < iters && rc == BLIP_OK; ++it) {
+            const int burst = std::max(8, rotate);
+            for (int it = 0; it <= kTuneSamples && rc == BLIP_OK; ++it) {
                 (void)hipEventRecord(e0, s);
-                // blocks rotate so a launch does not find its rows left in
-                // the caches by the launch before (as in a running simulation)
-                const double* pb = pos + 3 * npos * (int64_t)(it % rotate);
-                rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap, workspace,
-                                               P, OE, s)
-                             : launch_tiled(t, pb, npos, val, grad, lap, KIND_TILED, P, OE,
-                                            nullptr, nullptr, nullptr, nullptr, 0, false, s);
+                for (int b = 0; b < burst && rc == BLIP_OK; ++b) {
+                    const double* pb = pos + 3 * npos * (int64_t)((it * burst + b) % rotate);
+                    rc = batched ? enqueue_batched(t, pos, offsets, nw, npos, val, grad, lap,
+                                                   workspace, P, OE, s)
+                                 : launch_tiled(t, pb, npos, val, grad, lap, KIND_TILED, P, OE,
+                                                nullptr, nullptr, nullptr, nullptr, 0, false, s);
+                }
                 (void)hipEventRecord(e1, s);
                 e = hipEventSynchronize(e1);
-                if (e != hipSuccess) rc = fail_hip(e, "autotune sync");
+                if (e != hipSuccess && rc == BLIP_OK) rc = fail_hip(e, "autotune sync");
                 float ms = 0.0f;
-                if (rc == BLIP_OK && it >= 2) {
+                if (rc == BLIP_OK && it >= 1) {
                     (void)hipEventElapsedTime(&ms, e0, e1);
-                    ts.push_back(ms);
+                    ts.push_back(ms / burst);
                 }
             }
             if (rc != BLIP_OK) break;

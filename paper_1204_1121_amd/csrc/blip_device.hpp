@@ -8,10 +8,13 @@
 // orbital index fastest (Sec. II.B: the orbital index is the contiguous one,
 // which the coalesced mapping of Sec. IV.B relies on).
 //
-// Two kernel families live here:
+// Three kernel families live here:
 //   * plain_kernel: one workgroup per position, one lane per orbital, the 64
 //     Theta_s (and 4 derivative weights each) computed once into LDS -- the
 //     paper's coalesced mapping written for 64-wide wavefronts.
+//   * site_kernel: one wavefront per (position, orbital), one lane per
+//     stencil site, the 64 products summed across the wavefront -- the
+//     paper's non-coalesced comparison mappings, kept to measure them.
 //   * tiled_kernel: P positions per workgroup whose wrap and 1-D weights are
 //     prepared into LDS by P lanes; each wavefront then takes (position,
 //     orbital chunk) items and gathers the 64 coefficient rows with 4/8/16-byte
@@ -21,8 +24,9 @@
 //
 // Everything that decides an index (the wrap and the cell split) is FP64
 // with explicit round-to-nearest operations; sums are FP32 (FP64 in the debug
-// instantiation).  Each output element is produced by one lane in a fixed
-// order, so results do not depend on the tiling.
+// instantiation).  Each output element is produced in a fixed order (by one
+// lane, or by a fixed butterfly in site_kernel), so results do not depend on
+// the tiling.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -766,6 +770,54 @@ tiled_kernel(const KArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// One stencil site s = 16 m1 + 4 m2 + m3 of a position with cell i0 and
+// offsets f: th = (Theta_s, its Cartesian gradient, its Laplacian) with the
+// metric M, g applied in full, and the table row of the site.
+__device__ __forceinline__ void site_theta(const KArgs& a, const int (&i0)[3],
+                                           const double (&f)[3], int s, float (&th)[5],
+                                           uint32_t& row)
+{
+    const int m[3] = {s >> 4, (s >> 2) & 3, s & 3};
+    float p[3], dp[3], d2p[3];
+    for (int d = 0; d < 3; ++d) {
+        double w[4], d1[4], d2[4];
+        spline_weights(f[d], w, d1, d2);
+        p[d] = (float)w[m[d]];
+        dp[d] = (float)d1[m[d]];
+        d2p[d] = (float)d2[m[d]];
+    }
+    const float dt[3] = {dp[0] * p[1] * p[2], p[0] * dp[1] * p[2], p[0] * p[1] * dp[2]};
+    th[0] = p[0] * p[1] * p[2];
+    for (int c = 0; c < 3; ++c)
+        th[1 + c] = (float)a.M[c * 3] * dt[0] + (float)a.M[c * 3 + 1] * dt[1] +
+                    (float)a.M[c * 3 + 2] * dt[2];
+    const float h11 = d2p[0] * p[1] * p[2], h22 = p[0] * d2p[1] * p[2],
+                h33 = p[0] * p[1] * d2p[2];
+    const float h12 = dp[0] * dp[1] * p[2], h13 = dp[0] * p[1] * dp[2],
+                h23 = p[0] * dp[1] * dp[2];
+    th[4] = (float)a.g[0] * h11 + (float)a.g[1] * h22 + (float)a.g[2] * h33 +
+            2.0f * ((float)a.g[3] * h12 + (float)a.g[4] * h13 + (float)a.g[5] * h23);
+    const uint32_t i1 = wrap_index(i0[0] - 1 + m[0], a.n1);
+    const uint32_t i2 = wrap_index(i0[1] - 1 + m[1], a.n2);
+    const uint32_t i3 = wrap_index(i0[2] - 1 + m[2], a.n3);
+    row = (i1 * (uint32_t)a.n2 + i2) * (uint32_t)a.n3 + i3;
+}
+
+// G consecutive elements of one row as FP32 (G = 1 for 2-byte types reads a
+// single 16-bit element).
+template <class E, int G>
+__device__ __forceinline__ void load_row_elems(const char* rp, float (&x)[G])
+{
+    if constexpr (G == 1 && E::bytes == 2) {
+        const uint32_t h = *reinterpret_cast<const uint16_t*>(rp);
+        if constexpr (__is_same(E, BF16)) x[0] = __uint_as_float(h << 16);
+        else x[0] = (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+    } else {
+        load_elems<E, G, float>(rp, x);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Plain kernel: one workgroup per position; thread s < 64 computes Theta_s
 // and its Cartesian gradient and Laplacian into LDS; each thread then owns
 // one orbital (a complex pair when the Bloch factor is applied) and sums the
@@ -801,31 +853,11 @@ plain_kernel(const KArgs a)
     }
     __syncthreads();
     if (threadIdx.x < 64) {
-        const int s = threadIdx.x;
-        const int m[3] = {s >> 4, (s >> 2) & 3, s & 3};
-        float p[3], dp[3], d2p[3];
-        for (int d = 0; d < 3; ++d) {
-            double w[4], d1[4], d2[4];
-            spline_weights((double)s_f[d], w, d1, d2);
-            p[d] = (float)w[m[d]];
-            dp[d] = (float)d1[m[d]];
-            d2p[d] = (float)d2[m[d]];
-        }
-        const float dt[3] = {dp[0] * p[1] * p[2], p[0] * dp[1] * p[2], p[0] * p[1] * dp[2]};
-        th[s][0] = p[0] * p[1] * p[2];
-        for (int c = 0; c < 3; ++c)
-            th[s][1 + c] = (float)a.M[c * 3] * dt[0] + (float)a.M[c * 3 + 1] * dt[1] +
-                           (float)a.M[c * 3 + 2] * dt[2];
-        const float h11 = d2p[0] * p[1] * p[2], h22 = p[0] * d2p[1] * p[2],
-                    h33 = p[0] * p[1] * d2p[2];
-        const float h12 = dp[0] * dp[1] * p[2], h13 = dp[0] * p[1] * dp[2],
-                    h23 = p[0] * dp[1] * dp[2];
-        th[s][4] = (float)a.g[0] * h11 + (float)a.g[1] * h22 + (float)a.g[2] * h33 +
-                   2.0f * ((float)a.g[3] * h12 + (float)a.g[4] * h13 + (float)a.g[5] * h23);
-        const uint32_t i1 = wrap_index(s_i0[0] - 1 + m[0], a.n1);
-        const uint32_t i2 = wrap_index(s_i0[1] - 1 + m[1], a.n2);
-        const uint32_t i3 = wrap_index(s_i0[2] - 1 + m[2], a.n3);
-        rows[s] = (i1 * (uint32_t)a.n2 + i2) * (uint32_t)a.n3 + i3;
+        const int i0[3] = {s_i0[0], s_i0[1], s_i0[2]};
+        const double f[3] = {(double)s_f[0], (double)s_f[1], (double)s_f[2]};
+        float t5[5];
+        site_theta(a, i0, f, threadIdx.x, t5, rows[threadIdx.x]);
+        for (int q = 0; q < 5; ++q) th[threadIdx.x][q] = t5[q];
     }
     __syncthreads();
     constexpr int G = BLOCH ? 2 : 1;     // elements per thread
@@ -837,13 +869,7 @@ plain_kernel(const KArgs a)
         for (int s = 0; s < 64; ++s) {
             const char* rp = a.coef + (int64_t)rows[s] * a.row_bytes + (int64_t)e0 * E::bytes;
             float x[G];
-            if constexpr (G == 1 && E::bytes == 2) {
-                const uint32_t h = *reinterpret_cast<const uint16_t*>(rp);
-                if constexpr (__is_same(E, BF16)) x[0] = __uint_as_float(h << 16);
-                else x[0] = (float)__builtin_bit_cast(_Float16, (uint16_t)h);
-            } else {
-                load_elems<E, G, float>(rp, x);
-            }
+            load_row_elems<E, G>(rp, x);
             for (int e = 0; e < G; ++e) {
                 acc[0][e] = fma_(th[s][0], x[e], acc[0][e]);
                 if constexpr (FULL) {
@@ -869,6 +895,85 @@ plain_kernel(const KArgs a)
             if (e0 + e >= W) break;
             val[j * W + e0 + e] = res[0][e];
             if constexpr (FULL) {
+                for (int c = 0; c < 3; ++c) grad[(j * 3 + c) * W + e0 + e] = res[1 + c][e];
+                lap[j * W + e0 + e] = res[4][e];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Site-parallel kernel: the paper's comparison mappings that spread the
+// stencil sum of Eq. (11.12.24.1) over threads (Sec. IV.C, implementations
+// (1) and (2)).  A 64-lane workgroup takes one (position j, orbital l) item
+// at a time; lane s multiplies site s's weights by a_{l,s} and a butterfly
+// over the wavefront adds the 64 terms (every lane ends with the same sums,
+// in a fixed order).  Over a block of positions this is the
+// quasi-simultaneous non-coalesced mapping; launched once per position it is
+// the particle-by-particle one.  Lanes of a wavefront read 64 different
+// rows, so no load is coalesced: this kernel exists to measure that.
+template <class E, bool FULL, bool BLOCH>
+__global__ void __launch_bounds__(kWave)
+site_kernel(const KArgs a)
+{
+    constexpr int G = BLOCH ? 2 : 1;       // elements per orbital
+    constexpr int NQ = FULL ? 5 : 1;
+    const int nl = a.W / G;
+    const int64_t items = a.npos * (int64_t)nl;
+    const int s = threadIdx.x;
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t j = item / nl;
+        const int e0 = (int)(item - j * nl) * G;
+        const double* pp = a.pos + 3 * j;
+        double r[3] = {pp[0], pp[1], pp[2]};
+        bool bad = false;
+        int i0[3];
+        double f[3];
+        wrap_split(a, r, i0, f, bad);
+        float th[5];
+        uint32_t row;
+        site_theta(a, i0, f, s, th, row);
+        float x[G];
+        load_row_elems<E, G>(a.coef + (int64_t)row * a.row_bytes + (int64_t)e0 * E::bytes, x);
+        float v[5][G];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int e = 0; e < G; ++e) v[q][e] = th[q] * x[e];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int e = 0; e < G; ++e) v[q][e] += __shfl_xor(v[q][e], off, kWave);
+        if (s != 0) continue;
+        float res[5][G];
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                res[q][e] = q < NQ ? (__is_same(E, F16) ? v[q][e] * a.out_scale : v[q][e]) : 0.0f;
+        if constexpr (BLOCH) {
+            float cph = 1.0f, sph = 0.0f;
+            if (!bad) {
+                const double kr = a.k[0] * r[0] + a.k[1] * r[1] + a.k[2] * r[2];
+                double sk, ck;
+                sincos(kr, &sk, &ck);
+                cph = (float)ck;
+                sph = (float)sk;
+            }
+            apply_bloch<FULL, G>(a, cph, sph, res);
+        }
+        if (bad)
+            for (int q = 0; q < 5; ++q)
+                for (int e = 0; e < G; ++e) res[q][e] = __builtin_nanf("");
+        const int W = a.W;
+        float* val = static_cast<float*>(a.val);
+        for (int e = 0; e < G; ++e) val[j * W + e0 + e] = res[0][e];
+        if constexpr (FULL) {
+            float* grad = static_cast<float*>(a.grad);
+            float* lap = static_cast<float*>(a.lap);
+            for (int e = 0; e < G; ++e) {
                 for (int c = 0; c < 3; ++c) grad[(j * 3 + c) * W + e0 + e] = res[1 + c][e];
                 lap[j * W + e0 + e] = res[4][e];
             }

@@ -2,11 +2,13 @@
 // blip_launch_<type>.hip instantiates launch_eval<E> and launch_quantize<E>.
 #pragma once
 
+#include <algorithm>
+
 #include "blip_device.hpp"
 
 namespace blip {
 
-enum KernelKind { KIND_PLAIN = 1, KIND_TILED = 2, KIND_F64ACC = 3 };
+enum KernelKind { KIND_PLAIN = 1, KIND_TILED = 2, KIND_F64ACC = 3, KIND_SITE = 4 };
 
 struct Cfg {
     int kind;      // KernelKind
@@ -115,12 +117,27 @@ hipError_t go_plain(const KArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// One 64-lane workgroup per (position, orbital) item, grid-strided beyond
+// 2^22 items.
+template <class E, bool FULL, bool BLOCH>
+hipError_t go_site(const KArgs& a, hipStream_t s)
+{
+    const int64_t items = a.npos * (int64_t)(BLOCH ? a.W / 2 : a.W);
+    const unsigned grid = (unsigned)std::min<int64_t>(items, (int64_t)1 << 22);
+    hipLaunchKernelGGL((site_kernel<E, FULL, BLOCH>), dim3(grid), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace detail
 
 template <class E>
 hipError_t launch_eval(const KArgs& a, const Cfg& c, hipStream_t s)
 {
     using namespace detail;
+    if (c.kind == KIND_SITE) {
+        if (c.full) return c.bloch ? go_site<E, true, true>(a, s) : go_site<E, true, false>(a, s);
+        return c.bloch ? go_site<E, false, true>(a, s) : go_site<E, false, false>(a, s);
+    }
     if (c.kind == KIND_PLAIN) {
         if (c.full) return c.bloch ? go_plain<E, true, true>(a, s) : go_plain<E, true, false>(a, s);
         return c.bloch ? go_plain<E, false, true>(a, s) : go_plain<E, false, false>(a, s);

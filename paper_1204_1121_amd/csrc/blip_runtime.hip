@@ -317,9 +317,10 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
     int kind = KIND_TILED, P = 0, OE = 0;
     if (opts) {
         if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
-        if (opts->kernel < BLIP_KERNEL_AUTO || opts->kernel > BLIP_KERNEL_F64ACC)
+        if (opts->kernel < BLIP_KERNEL_AUTO || opts->kernel > BLIP_KERNEL_SITE)
             return fail(BLIP_E_ARG, "unknown kernel %d", opts->kernel);
         if (opts->kernel == BLIP_KERNEL_PLAIN) kind = KIND_PLAIN;
+        if (opts->kernel == BLIP_KERNEL_SITE) kind = KIND_SITE;
         if (opts->kernel == BLIP_KERNEL_F64ACC) {
             if (t->storage != BLIP_F32)
                 return fail(BLIP_E_DTYPE, "the FP64-accumulate kernel needs a BLIP_F32 table");
@@ -342,7 +343,7 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
     if (P == 0) P = P0;
     if (OE == 0) OE = OE0;
     if (kind == KIND_F64ACC && OE > 4) OE = 4;
-    if (kind == KIND_PLAIN) {
+    if (kind == KIND_PLAIN || kind == KIND_SITE) {
         KArgs a;
         fill_table_args(t, a);
         a.pos = pos;

@@ -3,8 +3,11 @@
 blip_autotune picks the fastest (positions per workgroup P, table elements
 per lane o) on the caller's buffers; this module keeps the winners in a JSON
 file keyed by architecture, storage dtype, orbital count, grid, path (single
-block or batched) and the power-of-two size bucket, and restores them into
-a table with blip_set_shape, so a run does not need to re-tune.
+block or batched), outputs (with derivatives, or values only) and the
+power-of-two size bucket, and restores them into a table with
+blip_set_shape, so a run does not need to re-tune.  A table holds one shape
+per size bucket, so a caller that uses one table for both output modes
+restores the mode it runs.
 """
 from __future__ import annotations
 
@@ -22,10 +25,11 @@ def bucket(npos: int) -> int:
     return lo
 
 
-def key(table, npos: int, batched: bool, arch: str = "gfx950") -> str:
+def key(table, npos: int, batched: bool, values_only: bool = False,
+        arch: str = "gfx950") -> str:
     n1, n2, n3 = table.n
-    return (f"{arch}/{table.storage}/L{table.norb}/{n1}x{n2}x{n3}/"
-            f"{'batched' if batched else 'block'}/{bucket(npos)}")
+    path = ("batched" if batched else "block") + ("-values" if values_only else "")
+    return f"{arch}/{table.storage}/L{table.norb}/{n1}x{n2}x{n3}/{path}/{bucket(npos)}"
 
 
 class TuneCache:
@@ -36,19 +40,20 @@ class TuneCache:
             with open(path) as f:
                 self.entries = json.load(f)
 
-    def get(self, table, npos: int, batched: bool = False):
-        return self.entries.get(key(table, npos, batched))
+    def get(self, table, npos: int, batched: bool = False, values_only: bool = False):
+        return self.entries.get(key(table, npos, batched, values_only))
 
-    def put(self, table, npos: int, batched: bool, best: dict, note: str = "") -> None:
+    def put(self, table, npos: int, batched: bool, best: dict, note: str = "",
+            values_only: bool = False) -> None:
         e = {"tile_pos": int(best["tile_pos"]), "vec": int(best["vec"]),
              "us": float(best["us"])}
         if note:
             e["note"] = note
-        self.entries[key(table, npos, batched)] = e
+        self.entries[key(table, npos, batched, values_only)] = e
 
-    def apply(self, table, npos: int, batched: bool = False) -> bool:
+    def apply(self, table, npos: int, batched: bool = False, values_only: bool = False) -> bool:
         """Set the cached shape on the table; False if none is cached."""
-        e = self.get(table, npos, batched)
+        e = self.get(table, npos, batched, values_only)
         if e is None:
             return False
         table.set_shape(npos, e["tile_pos"], e["vec"], batched=batched)

@@ -73,6 +73,7 @@ def test_small_tiled_and_plain(small):
     check(gpu_eval(t, pos), ref, FP32_TOL, "tiled vs oracle(fp32 table)")
     check(gpu_eval(t, pos), ref64, FP32_TOL, "tiled vs oracle(fp64 master)")
     check(gpu_eval(t, pos, kernel="plain"), ref, FP32_TOL, "plain vs oracle")
+    check(gpu_eval(t, pos, kernel="site"), ref, FP32_TOL, "site-parallel vs oracle")
 
 
 def test_small_fp64_accumulate(small):
@@ -119,6 +120,7 @@ def test_ragged_orbitals_and_tiles(blip, L):
             for k in y:
                 np.testing.assert_array_equal(y[k], base[k])
     check(gpu_eval(t, pos, kernel="plain"), ref, FP32_TOL, "plain")
+    check(gpu_eval(t, pos, kernel="site"), ref, FP32_TOL, "site-parallel")
     t.free()
 
 
@@ -134,6 +136,7 @@ def test_general_lattice(blip):
     ref = oracle.evaluate(SKEW, n, c, pos, nthreads=4)
     check(gpu_eval(t, pos), ref, FP32_TOL, "tiled")
     check(gpu_eval(t, pos, kernel="plain"), ref, FP32_TOL, "plain")
+    check(gpu_eval(t, pos, kernel="site"), ref, FP32_TOL, "site-parallel")
     check(gpu_eval(t, pos, kernel="f64acc", vec=1), ref, 1e-12, "f64acc")
     t.free()
 
@@ -179,9 +182,12 @@ def test_edge_positions(blip):
         assert np.all(np.isfinite(y[k][fin])), k
     sub = {k: v[fin] for k, v in y.items()}
     check(sub, {k: v[fin] for k, v in ref.items()}, FP32_TOL, "finite edge rows")
-    yp = gpu_eval(t, pos, kernel="plain")
-    for k in ("val", "grad", "lap"):
-        assert np.all(np.isnan(yp[k][~fin])), k
+    for kern in ("plain", "site"):
+        yp = gpu_eval(t, pos, kernel=kern)
+        for k in ("val", "grad", "lap"):
+            assert np.all(np.isnan(yp[k][~fin])), (kern, k)
+        check({k: v[fin] for k, v in yp.items()}, {k: v[fin] for k, v in ref.items()},
+              FP32_TOL, f"{kern} finite edge rows")
     # npos = 0 enqueues nothing and succeeds
     p0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
     v, g, l = t.eval(p0)
@@ -238,6 +244,7 @@ def test_tio2_blocks(tio2, B):
     ref = oracle.evaluate(spec.lattice, spec.n, c, pos, nthreads=8)
     check(gpu_eval(t, pos), ref, FP32_TOL, "tuned")
     check(gpu_eval(t, pos, kernel="plain"), ref, FP32_TOL, "plain")
+    check(gpu_eval(t, pos, kernel="site"), ref, FP32_TOL, "site-parallel")
 
 
 def test_tio2_values_only(tio2):
@@ -255,12 +262,14 @@ def test_tio2_reduced_precision(blip, tio2, storage):
     t = blip.Table(spec.lattice, spec.n, c, storage)
     pos = wl.move_block(spec, 1536, block=2)
     y = gpu_eval(t, pos)
+    ys = gpu_eval(t, pos, kernel="site")
     t.free()
     ref = oracle.evaluate(spec.lattice, spec.n, c, pos, nthreads=8)
     check(y, ref, HALF_TOL, f"{storage} vs fp32 master")
     q = quantize_bf16(c) if storage == "bf16" else quantize_f16_scaled(c)
     refq = oracle.evaluate(spec.lattice, spec.n, q, pos, nthreads=8)
     check(y, refq, FP32_TOL, f"{storage} vs oracle on quantised table")
+    check(ys, refq, FP32_TOL, f"{storage} site-parallel vs oracle on quantised table")
 
 
 # ---------------------------------------------------------------------------
@@ -284,10 +293,12 @@ def test_complex_kpoint(blip, tio2c, storage):
     t = blip.Table(spec.lattice, spec.n, c, storage, kvec=spec.kvec)
     y = gpu_eval(t, pos)
     yp = gpu_eval(t, pos, kernel="plain")
+    ys = gpu_eval(t, pos, kernel="site")
     t.free()
     tol = FP32_TOL if storage == "c64" else HALF_TOL
     check(y, ref, tol, f"{storage} tuned vs c64 master")
     check(yp, ref, tol, f"{storage} plain vs c64 master")
+    check(ys, ref, tol, f"{storage} site-parallel vs c64 master")
     if storage != "c64":
         q = quantize_bf16(c) if storage == "cbf16" else quantize_f16_scaled(c)
         refq = oracle.evaluate(spec.lattice, spec.n, q, pos, kvec=spec.kvec, nthreads=8)
@@ -336,6 +347,10 @@ def test_values_only_complex_and_skewed(blip):
         check(full, ref, tol, f"{storage} full")
         pl = gpu_eval(t, pos, kernel="plain", grad=False)
         check({"val": pl["val"]}, {"val": ref["val"]}, tol, f"{storage} plain values")
+        sv = gpu_eval(t, pos, kernel="site", grad=False)
+        sf = gpu_eval(t, pos, kernel="site")
+        np.testing.assert_array_equal(sv["val"], sf["val"])
+        check(sf, ref, tol, f"{storage} site-parallel full")
         t.free()
 
 
