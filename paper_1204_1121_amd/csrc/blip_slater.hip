@@ -42,9 +42,11 @@ namespace {
 
 constexpr int kSmChunk = 32;        // moves applied per launch
 constexpr int kSmThreads = 256;     // four waves
-constexpr int kSmRows = 8;          // rows of B per workgroup (one matrix: more workgroups)
-constexpr int kSmRowsBatched = 16;  // rows per workgroup when many matrices fill the chip
-constexpr int kSmPiece = 128;       // columns per pass inside a column tile
+constexpr int kSmRows = 16;         // rows of B per workgroup: one matrix-core tile
+constexpr int kSmTile = 16;         // columns of B per matrix-core tile
+constexpr int kSmWaves = kSmThreads / 64;
+constexpr int kSmAhead = 2;         // tiles loaded ahead of the one being computed
+constexpr int kSmPiece = 128;       // column tiles are a multiple of this wide
 constexpr int kSmPad = kSmChunk + 1;
 constexpr int64_t kSmMaxN = 4096;
 constexpr int kSmMaxTiles = 4;      // column tiles (partial sums of V per row)
@@ -79,6 +81,8 @@ struct SmArgs {
     int64_t ws_mstride;      // doubles between matrices in the workspace
     int64_t ratio_ld;        // ratios of matrix q start at ratio + q * ratio_ld
     const double* sinv;      // [nmat] S^{-1} of the applied chunk, from sm_sinv_kernel
+    int vec_b;               // 1: rows of B (every matrix) start 16-byte aligned
+    int vec_u;               // 1: rows of u (every matrix) start 16-byte aligned
 };
 
 // Column tiles: at most kSmMaxTiles per row (so summing V's partials stays
@@ -105,16 +109,15 @@ inline int64_t sm_ws_doubles(int64_t n)
     return (d + 31) / 32 * 32;   // keep each matrix's block 256-byte aligned
 }
 
-// What a thread reads for one kSmPiece-wide pass: its column of B on its RPT
-// rows, the chunk's moved rows R at that column, and (for the next chunk) 16
-// new-orbital values at that column.  Loaded together so their latencies
-// overlap.
-template <int RPT>
-struct SmFrag {
-    double b[RPT];
-    double r[kSmChunk];
-    float u[16];
-};
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// FP64 matrix-core product on one wavefront, D = A B + C with A 16 x 4 and
+// B 4 x 16: lane l supplies A[l%16][l/16] and B[l/16][l%16], and element r of
+// C and D is entry (4r + l/16, l%16).
+__device__ __forceinline__ v4d mfma_f64_16x16x4(double a, double b, v4d c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Moves of matrix q in a batched launch: kp of chunk c-1 and kn of chunk c.
 __device__ __forceinline__ void sm_batched_counts(const SmArgs& a, int q, int& kp, int& kn)
@@ -230,28 +233,42 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
         a.ratio[(int64_t)q * a.ratio_ld + (int64_t)(a.chunk - 1) * kSmChunk + tid] = piv[tid];
 }
 
-// One launch: workgroup (x, y) applies chunk p to rows [8x, 8x+8) and
+// One launch: workgroup (x, y) applies chunk p to rows [16x, 16x+16) and
 // columns [y*tl, (y+1)*tl) of B, copies the moved rows of chunk n into Rn,
 // and writes its columns' share of V = B' U^T for chunk n to Pn[y].  In the
 // batched form blockIdx.z is the matrix and S^{-1} comes from sm_sinv_kernel.
 //
-// Loads are written without data-dependent branches: addresses are clamped
-// into bounds and unwanted values replaced by zero afterwards, so each group
-// of loads is issued back to back and waited for once.  Only the uniform
-// tests kp > 0 and kn > 0 guard buffers that may be absent.
+// Both products run on the FP64 matrix cores, one 16 x 16 tile of B (16 rows,
+// 16 columns) at a time per wavefront.  Slot i of a tile (the matrix-core
+// row index of the update, 0..15) stands for column c + 4 (i%4) + i/4:
+//   * the update is computed transposed, B'^T = B^T + R^T (-Y)^T, so element
+//     r of lane l's accumulator is slot 4r + l/16, i.e. B'[row l%16][column
+//     c + 4 (l/16) + r]: four consecutive columns of one row per lane, read
+//     and written as two 16-byte accesses;
+//   * that layout is directly the A operand of V += B' U^T, k-step r taking
+//     the columns c + 4q + r (q = l/16), and the matching U values of a lane
+//     are again four consecutive floats, one 16-byte load.
+// Each tile takes 8 + 8 matrix-core operations.  Wavefront w takes the
+// tiles w, w+4, ... of a column tile, and the four partial V tiles are added
+// in wavefront order.
 //
-template <bool BATCHED, int ROWS>
+// Loads are written without data-dependent branches: addresses are clamped
+// into bounds and unwanted values replaced by zero, so each group of loads is
+// issued back to back.  Wide accesses are used for whole tiles when the host
+// has found the rows 16-byte aligned; a ragged last tile takes the clamped
+// scalar path, which reads the same values.  Only the uniform tests kp > 0
+// and kn > 0 guard buffers that may be absent.
+template <bool BATCHED>
 __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
-    constexpr int RPT = ROWS / 2;          // rows per thread in the update
-    constexpr int VPT = ROWS / 8;          // entries of V (and Y) per thread
+    constexpr int ROWS = kSmRows;
+    constexpr int VPT = ROWS / 8;               // entries of V - E (and Y) per thread
     __shared__ double bc[2][2][kSmChunk];       // pivot row / column, double-buffered
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
     __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
     __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
     __shared__ double piv[kSmChunk];
-    __shared__ double Bt[ROWS][kSmPiece];       // updated piece of B
-    __shared__ float Ut[kSmPiece][kSmPad];      // piece of U^T of the next chunk
+    __shared__ double Vw[kSmWaves][ROWS][kSmChunk + 1];   // per-wavefront partial V
     __shared__ int lcolp[kSmChunk], lcoln[kSmChunk], lurow[kSmChunk];
     __shared__ int slot[ROWS];                  // row's index in the next chunk, or -1
 
@@ -278,10 +295,6 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         Rn += wo;
     }
     const int i0 = blockIdx.x * ROWS;
-    const int c0 = blockIdx.y * a.tl;
-    const int cend = min(n, c0 + a.tl);
-    const int cc = tid % kSmPiece;                                  // column within a piece
-    const int h = __builtin_amdgcn_readfirstlane(tid / kSmPiece);   // rows RPT*h.. (per wave)
 
     // index lists into LDS
     if constexpr (BATCHED) {
@@ -307,32 +320,6 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         }
     }
     __syncthreads();
-
-    // A lane whose column is past the tile reads the tile's last column (in
-    // bounds) and its results are never stored; rows past n read row n-1.
-    // Zeroing uses only uniform conditions, so no load sits behind a branch.
-    auto fetch = [&](int q0, SmFrag<RPT>& f) {
-        const int c = q0 + cc;
-        const int cl = c < cend ? c : cend - 1;
-#pragma unroll
-        for (int rr = 0; rr < RPT; ++rr) {
-            const int i = i0 + RPT * h + rr;   // uniform per wave
-            f.b[rr] = inv[(int64_t)(i < n ? i : n - 1) * a.ld + cl];
-        }
-        if (kp > 0) {
-#pragma unroll
-            for (int m = 0; m < kSmChunk; ++m) f.r[m] = Rp[(int64_t)(m < kp ? m : kp - 1) * n + cl];
-        }
-        if (kn > 0) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int m = 16 * h + k;   // uniform per wave
-                f.u[k] = u[(int64_t)lurow[m < kn ? m : kn - 1] * a.u_ld + cl];
-            }
-        }
-    };
-    SmFrag<RPT> f;
-    fetch(c0, f);   // in flight while S is assembled and eliminated
 
     if (tid < ROWS) {
         int sl = -1;
@@ -387,85 +374,180 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     }
     __syncthreads();
 
-    // Pieces of kSmPiece columns: B' = B - Y R, the moved rows of the next
-    // chunk copied to Rn, then this piece's share of V = B' U^T.
-    const int vr0 = tid / kSmChunk, vm = tid % kSmChunk;   // V entries: rows vr0 + 8k
-    double vacc[VPT][4];                                    // four chains each, added in order
+    // Matrix-core tiles.  Lane l works on row i0 + l%16; its lane group
+    // g = l/16 selects the columns c + 4g .. c + 4g + 3 of a tile and the
+    // moves 4s + g.
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int i = i0 + lr;
+    const int irow = i < n ? i : n - 1;
+    const int sl = slot[lr];
+    double yop[kSmChunk / 4];   // (-Y)^T operand: -Y[row][4s + g]
+    if (kp > 0) {
 #pragma unroll
-    for (int k = 0; k < VPT; ++k)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) vacc[k][t] = 0.0;
-    for (int q0 = c0; q0 < cend; q0 += kSmPiece) {
-        const int c = q0 + cc;
-        double acc[RPT];
-#pragma unroll
-        for (int rr = 0; rr < RPT; ++rr) acc[rr] = f.b[rr];
-        if (kp > 0) {
-            // all 32 terms: Y is zero past kp and the rows of f.r past kp are
-            // clamped copies, so the loop has no branches and its LDS reads
-            // can all be in flight together
-#pragma unroll
-            for (int m = 0; m < kSmChunk; ++m) {
-#pragma unroll
-                for (int rr = 0; rr < RPT; ++rr) acc[rr] = fma(-Y[RPT * h + rr][m], f.r[m], acc[rr]);
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < RPT; ++rr) {
-            const int r = RPT * h + rr;
-            const int i = i0 + r;
-            if (c < cend && i < n) {
-                if (kp > 0) inv[(int64_t)i * a.ld + c] = acc[rr];
-                if (slot[r] >= 0) Rn[(int64_t)slot[r] * n + c] = acc[rr];
-            }
-        }
-        if (kn > 0) {
-#pragma unroll
-            for (int rr = 0; rr < RPT; ++rr)
-                Bt[RPT * h + rr][cc] = (c < cend && i0 + RPT * h + rr < n) ? acc[rr] : 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                Ut[cc][16 * h + k] = (c < cend && 16 * h + k < kn) ? f.u[k] : 0.0f;
-        }
-        if (q0 + kSmPiece < cend) fetch(q0 + kSmPiece, f);   // next piece, in flight below
-        if (kn > 0) {
-            __syncthreads();
-#pragma unroll 4
-            for (int j = 0; j < kSmPiece; j += 4) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const double uv = (double)Ut[j + t][vm];
-#pragma unroll
-                    for (int k = 0; k < VPT; ++k) vacc[k][t] = fma(Bt[vr0 + 8 * k][j + t], uv, vacc[k][t]);
-                }
-            }
-            __syncthreads();
-        }
+        for (int s4 = 0; s4 < kSmChunk / 4; ++s4) yop[s4] = -Y[lr][4 * s4 + g];
     }
+    int urow[2] = {0, 0};       // rows of u for moves lr and 16 + lr
     if (kn > 0) {
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-            const int i = i0 + vr0 + 8 * k;
-            if (i < n && vm < kn)
-                Pn[((int64_t)blockIdx.y * n + i) * kSmChunk + vm] =
-                    (vacc[k][0] + vacc[k][1]) + (vacc[k][2] + vacc[k][3]);
+        for (int mb = 0; mb < 2; ++mb) {
+            const int m = 16 * mb + lr;
+            urow[mb] = lurow[m < kn ? m : kn - 1];
+        }
+    }
+
+    // What a lane reads for one tile at column c: its 4 entries of B, the
+    // moved rows R at the column of slot l%16, and the next chunk's new
+    // orbitals at its 4 columns.
+    struct TileIn {
+        v4d b;
+        double r[kSmChunk / 4];
+        float u[2][4];
+    };
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int cq = 4 * g;   // first of the lane's columns within a tile
+    auto load_tile = [&](int c, int cend, TileIn& in) {
+        const bool whole = c + kSmTile <= cend;   // uniform per wavefront
+        const double* brow = inv + (int64_t)irow * a.ld;
+        if (a.vec_b && whole) {
+            const d2 x0 = *reinterpret_cast<const d2*>(brow + c + cq);
+            const d2 x1 = *reinterpret_cast<const d2*>(brow + c + cq + 2);
+            in.b = v4d{x0.x, x0.y, x1.x, x1.y};
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int col = c + cq + r;
+                in.b[r] = brow[col < cend ? col : cend - 1];
+            }
+        }
+        if (kp > 0) {
+            const int cs = c + 4 * (lr & 3) + (lr >> 2);   // column of slot lr
+            const int col = cs < cend ? cs : cend - 1;
+#pragma unroll
+            for (int s4 = 0; s4 < kSmChunk / 4; ++s4) {
+                const int m = 4 * s4 + g;
+                in.r[s4] = Rp[(int64_t)(m < kp ? m : kp - 1) * n + col];
+            }
+        }
+        if (kn > 0) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const float* urw = u + (int64_t)urow[mb] * a.u_ld;
+                if (a.vec_u && whole) {
+                    const f4 x = *reinterpret_cast<const f4*>(urw + c + cq);
+                    in.u[mb][0] = x.x;
+                    in.u[mb][1] = x.y;
+                    in.u[mb][2] = x.z;
+                    in.u[mb][3] = x.w;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int col = c + cq + r;
+                        in.u[mb][r] = urw[col < cend ? col : cend - 1];
+                    }
+                }
+            }
+        }
+    };
+
+    // The batched form walks every column tile of its rows (one prologue per
+    // matrix row block); the single form takes the column tile blockIdx.y.
+    // V partials are kept per column tile either way, in the same order.
+    const int y0 = BATCHED ? 0 : (int)blockIdx.y;
+    const int y1 = BATCHED ? nct : y0 + 1;
+    for (int y = y0; y < y1; ++y) {
+        const int c0 = y * a.tl;
+        const int cend = min(n, c0 + a.tl);
+        const int ntile = (cend - c0 + kSmTile - 1) / kSmTile;
+        v4d vacc[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) vacc[mb] = v4d{0.0, 0.0, 0.0, 0.0};
+        // Wavefront w takes tiles w, w+4, ...: K of them.  Loads run kSmAhead
+        // tiles ahead of the tile being computed, through a ring of buffers
+        // whose indices are compile-time constants (the loop is unrolled by
+        // the ring length); the next loads go out before this tile's stores,
+        // so waiting for a tile never waits for stores.
+        const int K = w < ntile ? (ntile - w + kSmWaves - 1) / kSmWaves : 0;
+        TileIn buf[kSmAhead + 1];
+#pragma unroll
+        for (int j = 0; j < kSmAhead; ++j)
+            if (j < K) load_tile(c0 + (w + kSmWaves * j) * kSmTile, cend, buf[j]);
+        for (int kb = 0; kb < K; kb += kSmAhead + 1) {
+#pragma unroll
+            for (int j = 0; j <= kSmAhead; ++j) {
+                const int k = kb + j;
+                if (k >= K) break;   // uniform per wavefront
+                if (k + kSmAhead < K)
+                    load_tile(c0 + (w + kSmWaves * (k + kSmAhead)) * kSmTile, cend,
+                              buf[(j + kSmAhead) % (kSmAhead + 1)]);
+                const TileIn& cur = buf[j];
+                const int c = c0 + (w + kSmWaves * k) * kSmTile;
+                v4d acc = cur.b;
+                // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
+                if (kp > 0) {
+#pragma unroll
+                    for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+                        acc = mfma_f64_16x16x4(cur.r[s4], yop[s4], acc);
+                }
+                if (kp > 0 && i < n) {
+                    double* brow = inv + (int64_t)i * a.ld;
+                    if (a.vec_b && c + kSmTile <= cend) {
+                        *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
+                        *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                    }
+                }
+                if (sl >= 0 && i < n) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (c + cq + r < cend) Rn[(int64_t)sl * n + c + cq + r] = acc[r];
+                }
+                // V += B' U^T, k-step r over the columns c + 4q + r (columns
+                // past the tile contribute zero)
+                if (kn > 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double bval = (c + cq + r < cend) ? acc[r] : 0.0;
+#pragma unroll
+                        for (int mb = 0; mb < 2; ++mb)
+                            vacc[mb] = mfma_f64_16x16x4(bval, (double)cur.u[mb][r], vacc[mb]);
+                    }
+                }
+            }
+        }
+        if (kn > 0) {
+            // element r of vacc[mb] is V[row 4r + g][move 16 mb + lr]
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Vw[w][4 * r + g][16 * mb + lr] = vacc[mb][r];
+            __syncthreads();
+            for (int e = tid; e < ROWS * kSmChunk; e += kSmThreads) {
+                const int row = e / kSmChunk, m = e % kSmChunk;
+                double v = Vw[0][row][m];
+#pragma unroll
+                for (int ww = 1; ww < kSmWaves; ++ww) v += Vw[ww][row][m];
+                if (i0 + row < n && m < kn)
+                    Pn[((int64_t)y * n + i0 + row) * kSmChunk + m] = v;
+            }
+            __syncthreads();   // Vw is rewritten for the next column tile
         }
     }
 }
 
 __global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
 {
-    sm_chunk_body<false, kSmRows>(a);
+    sm_chunk_body<false>(a);
 }
 
-// The 16-row tile takes 170 registers (two waves per SIMD); asking for three
-// waves spills two of them to scratch, and the third wave hides enough load
-// latency to make the batched step about 17% faster per matrix.  The 8-row
-// tile already fits three waves and is left to the compiler's choice.
-__global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
-void sm_chunk_batched_kernel(SmArgs a)
+__global__ __launch_bounds__(kSmThreads) void sm_chunk_batched_kernel(SmArgs a)
 {
-    sm_chunk_body<true, kSmRowsBatched>(a);
+    sm_chunk_body<true>(a);
 }
 
 hipError_t sm_launch(const SmArgs& a, hipStream_t s)
@@ -552,6 +634,8 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
         a.ld = inv_ld;
         a.u = u;
         a.u_ld = u_ld;
+        a.vec_b = aligned(inv, 16) && inv_ld % 2 == 0;
+        a.vec_u = u != nullptr && aligned(u, 16) && u_ld % 4 == 0;
         if (c > 0) {
             const size_t q = c - 1;
             a.kp = (int)len[q];
@@ -616,8 +700,8 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     double* S = ws + 2 * pv + (size_t)2 * kSmChunk * n;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int nchunks = (max_k + kSmChunk - 1) / kSmChunk;
-    const dim3 grid((unsigned)((n + kSmRowsBatched - 1) / kSmRowsBatched), (unsigned)sh.nct,
-                    (unsigned)nmat);
+    // one workgroup per (16-row block, matrix); it walks the column tiles
+    const dim3 grid((unsigned)((n + kSmRows - 1) / kSmRows), 1u, (unsigned)nmat);
 
     SmArgs a{};
     a.n = (int)n;
@@ -634,6 +718,8 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     a.acc_count = acc_count;
     a.inv_mstride = inv_mstride;
     a.u_mstride = u_mstride;
+    a.vec_b = aligned(inv, 16) && inv_ld % 2 == 0 && inv_mstride % 2 == 0;
+    a.vec_u = u != nullptr && aligned(u, 16) && u_ld % 4 == 0 && u_mstride % 4 == 0;
     a.ws_mstride = ws_m;
     a.ratio_ld = ratio_ld;
     a.sinv = S;
