@@ -42,10 +42,9 @@ namespace {
 
 constexpr int kSmChunk = 32;        // moves applied per launch
 constexpr int kSmThreads = 256;     // four waves
-constexpr int kSmRows = 16;         // rows of B per workgroup: one matrix-core tile
 constexpr int kSmTile = 16;         // columns of B per matrix-core tile
 constexpr int kSmWaves = kSmThreads / 64;
-constexpr int kSmAhead = 2;         // tiles loaded ahead of the one being computed
+constexpr int kSmAhead = 1;         // tiles loaded ahead of the one being computed
 constexpr int kSmPiece = 128;       // column tiles are a multiple of this wide
 constexpr int kSmPad = kSmChunk + 1;
 constexpr int64_t kSmMaxN = 4096;
@@ -258,10 +257,10 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 // has found the rows 16-byte aligned; a ragged last tile takes the clamped
 // scalar path, which reads the same values.  Only the uniform tests kp > 0
 // and kn > 0 guard buffers that may be absent.
-template <bool BATCHED>
+template <bool BATCHED, int RB>
 __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
-    constexpr int ROWS = kSmRows;
+    constexpr int ROWS = 16 * RB;               // rows of B: RB matrix-core row blocks
     constexpr int VPT = ROWS / 8;               // entries of V - E (and Y) per thread
     __shared__ double bc[2][2][kSmChunk];       // pivot row / column, double-buffered
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
@@ -380,13 +379,17 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    const int i = i0 + lr;
-    const int irow = i < n ? i : n - 1;
-    const int sl = slot[lr];
-    double yop[kSmChunk / 4];   // (-Y)^T operand: -Y[row][4s + g]
-    if (kp > 0) {
+    int irow[RB], sl[RB];
+    double yop[RB][kSmChunk / 4];   // (-Y)^T operands: -Y[row][4s + g]
 #pragma unroll
-        for (int s4 = 0; s4 < kSmChunk / 4; ++s4) yop[s4] = -Y[lr][4 * s4 + g];
+    for (int rb = 0; rb < RB; ++rb) {
+        const int i = i0 + 16 * rb + lr;
+        irow[rb] = i < n ? i : n - 1;
+        sl[rb] = i < n ? slot[16 * rb + lr] : -1;
+        if (kp > 0) {
+#pragma unroll
+            for (int s4 = 0; s4 < kSmChunk / 4; ++s4) yop[rb][s4] = -Y[16 * rb + lr][4 * s4 + g];
+        }
     }
     int urow[2] = {0, 0};       // rows of u for moves lr and 16 + lr
     if (kn > 0) {
@@ -401,7 +404,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // moved rows R at the column of slot l%16, and the next chunk's new
     // orbitals at its 4 columns.
     struct TileIn {
-        v4d b;
+        v4d b[RB];
         double r[kSmChunk / 4];
         float u[2][4];
     };
@@ -410,16 +413,19 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     const int cq = 4 * g;   // first of the lane's columns within a tile
     auto load_tile = [&](int c, int cend, TileIn& in) {
         const bool whole = c + kSmTile <= cend;   // uniform per wavefront
-        const double* brow = inv + (int64_t)irow * a.ld;
-        if (a.vec_b && whole) {
-            const d2 x0 = *reinterpret_cast<const d2*>(brow + c + cq);
-            const d2 x1 = *reinterpret_cast<const d2*>(brow + c + cq + 2);
-            in.b = v4d{x0.x, x0.y, x1.x, x1.y};
-        } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int col = c + cq + r;
-                in.b[r] = brow[col < cend ? col : cend - 1];
+        for (int rb = 0; rb < RB; ++rb) {
+            const double* brow = inv + (int64_t)irow[rb] * a.ld;
+            if (a.vec_b && whole) {
+                const d2 x0 = *reinterpret_cast<const d2*>(brow + c + cq);
+                const d2 x1 = *reinterpret_cast<const d2*>(brow + c + cq + 2);
+                in.b[rb] = v4d{x0.x, x0.y, x1.x, x1.y};
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int col = c + cq + r;
+                    in.b[rb][r] = brow[col < cend ? col : cend - 1];
+                }
             }
         }
         if (kp > 0) {
@@ -461,9 +467,11 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         const int c0 = y * a.tl;
         const int cend = min(n, c0 + a.tl);
         const int ntile = (cend - c0 + kSmTile - 1) / kSmTile;
-        v4d vacc[2];
+        v4d vacc[RB][2];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) vacc[mb] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) vacc[rb][mb] = v4d{0.0, 0.0, 0.0, 0.0};
         // Wavefront w takes tiles w, w+4, ...: K of them.  Loads run kSmAhead
         // tiles ahead of the tile being computed, through a ring of buffers
         // whose indices are compile-time constants (the loop is unrolled by
@@ -484,48 +492,55 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
                               buf[(j + kSmAhead) % (kSmAhead + 1)]);
                 const TileIn& cur = buf[j];
                 const int c = c0 + (w + kSmWaves * k) * kSmTile;
-                v4d acc = cur.b;
-                // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
-                if (kp > 0) {
 #pragma unroll
-                    for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
-                        acc = mfma_f64_16x16x4(cur.r[s4], yop[s4], acc);
-                }
-                if (kp > 0 && i < n) {
-                    double* brow = inv + (int64_t)i * a.ld;
-                    if (a.vec_b && c + kSmTile <= cend) {
-                        *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
-                        *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
-                    } else {
+                for (int rb = 0; rb < RB; ++rb) {
+                    v4d acc = cur.b[rb];
+                    // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
+                    if (kp > 0) {
+#pragma unroll
+                        for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+                            acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
+                    }
+                    const int i = i0 + 16 * rb + lr;
+                    if (kp > 0 && i < n) {
+                        double* brow = inv + (int64_t)i * a.ld;
+                        if (a.vec_b && c + kSmTile <= cend) {
+                            *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
+                            *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                        }
+                    }
+                    if (sl[rb] >= 0) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                            if (c + cq + r < cend) Rn[(int64_t)sl[rb] * n + c + cq + r] = acc[r];
                     }
-                }
-                if (sl >= 0 && i < n) {
+                    // V += B' U^T, k-step r over the columns c + 4q + r
+                    // (columns past the tile contribute zero)
+                    if (kn > 0) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (c + cq + r < cend) Rn[(int64_t)sl * n + c + cq + r] = acc[r];
-                }
-                // V += B' U^T, k-step r over the columns c + 4q + r (columns
-                // past the tile contribute zero)
-                if (kn > 0) {
+                        for (int r = 0; r < 4; ++r) {
+                            const double bval = (c + cq + r < cend) ? acc[r] : 0.0;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double bval = (c + cq + r < cend) ? acc[r] : 0.0;
-#pragma unroll
-                        for (int mb = 0; mb < 2; ++mb)
-                            vacc[mb] = mfma_f64_16x16x4(bval, (double)cur.u[mb][r], vacc[mb]);
+                            for (int mb = 0; mb < 2; ++mb)
+                                vacc[rb][mb] = mfma_f64_16x16x4(bval, (double)cur.u[mb][r], vacc[rb][mb]);
+                        }
                     }
                 }
             }
         }
         if (kn > 0) {
-            // element r of vacc[mb] is V[row 4r + g][move 16 mb + lr]
+            // element r of vacc[rb][mb] is V[row 16 rb + 4r + g][move 16 mb + lr]
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Vw[w][4 * r + g][16 * mb + lr] = vacc[mb][r];
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Vw[w][16 * rb + 4 * r + g][16 * mb + lr] = vacc[rb][mb][r];
             __syncthreads();
             for (int e = tid; e < ROWS * kSmChunk; e += kSmThreads) {
                 const int row = e / kSmChunk, m = e % kSmChunk;
@@ -540,19 +555,31 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     }
 }
 
-__global__ __launch_bounds__(kSmThreads) void sm_chunk_kernel(SmArgs a)
+// The row count of a workgroup only distributes work: every element goes
+// through the same operations in the same order with one or two row blocks.
+// The single-matrix form takes one (more workgroups for one matrix); the
+// batched form takes two when there are enough matrices to fill the chip,
+// so each R and U operand serves twice the rows.  Left to itself the
+// compiler gives the two-block body about 290 registers (one wavefront per
+// SIMD); asked for two wavefronts it fits 238 without spilling, and the
+// second hides load latency (44.6 against 55.5 us per matrix-step on the
+// batched update of 64 matrices).
+__global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void sm_chunk_kernel(SmArgs a)
 {
-    sm_chunk_body<false>(a);
+    sm_chunk_body<false, 1>(a);
 }
 
-__global__ __launch_bounds__(kSmThreads) void sm_chunk_batched_kernel(SmArgs a)
+template <int RB>
+__global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void sm_chunk_batched_kernel(SmArgs a)
 {
-    sm_chunk_body<true>(a);
+    sm_chunk_body<true, RB>(a);
 }
 
 hipError_t sm_launch(const SmArgs& a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.n + kSmRows - 1) / kSmRows), (unsigned)a.nct);
+    const dim3 grid((unsigned)((a.n + 15) / 16), (unsigned)a.nct);
     hipLaunchKernelGGL(sm_chunk_kernel, grid, dim3(kSmThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -700,8 +727,10 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     double* S = ws + 2 * pv + (size_t)2 * kSmChunk * n;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int nchunks = (max_k + kSmChunk - 1) / kSmChunk;
-    // one workgroup per (16-row block, matrix); it walks the column tiles
-    const dim3 grid((unsigned)((n + kSmRows - 1) / kSmRows), 1u, (unsigned)nmat);
+    // one workgroup per (row block, matrix); it walks the column tiles.  Two
+    // 16-row blocks per workgroup while that still gives 4 workgroups per CU.
+    const int rb = (n + 31) / 32 * (int64_t)nmat >= 4 * 256 ? 2 : 1;
+    const dim3 grid((unsigned)((n + 16 * rb - 1) / (16 * rb)), 1u, (unsigned)nmat);
 
     SmArgs a{};
     a.n = (int)n;
@@ -736,7 +765,10 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         }
         a.Pn = V[c & 1];
         a.Rn = R[c & 1];
-        hipLaunchKernelGGL(sm_chunk_batched_kernel, grid, dim3(kSmThreads), 0, s, a);
+        if (rb == 2)
+            hipLaunchKernelGGL(sm_chunk_batched_kernel<2>, grid, dim3(kSmThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL(sm_chunk_batched_kernel<1>, grid, dim3(kSmThreads), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail_hip(e, "sm_chunk_batched_kernel launch");
     }

@@ -131,8 +131,8 @@ def test_unmoved_electrons_leave_inverse(blip):
 
 @pytest.mark.parametrize("n", [1, 2, 33, 1024, 1025, 2049, 4096])
 def test_orders_and_row_tilings(blip, n):
-    """Every rows-per-workgroup variant (4 up to n = 1024, 2 up to 2048, 1
-    above), the smallest orders and the largest accepted one."""
+    """The smallest orders, ragged 16-row and 16-column tiles (33, 1025,
+    2049), one to four column tiles, and the largest accepted order."""
     k = min(n, 40)
     check(blip, *case(100 + n, n, k), label="order")
 
@@ -224,6 +224,38 @@ def test_batched_equals_single_bitwise(blip):
     want_b, want_r = slater.sm_update(invs[q], Us[q][lists[q]].astype(np.float64), lists[q])
     assert np.abs(got_inv[q] - want_b).max() <= 1e-10 * np.abs(want_b).max()
     np.testing.assert_allclose(got_r[q, : counts[q]], want_r, rtol=1e-9)
+
+
+def test_batched_two_row_blocks_equals_single_bitwise(blip):
+    """Enough matrices for the batched kernel to take two 16-row blocks per
+    workgroup (ceil(n/32) * nmat >= 1024): still bit for bit the single-matrix
+    result on sampled matrices, with a ragged n and uneven counts."""
+    n, nmat = 200, 160
+    rng = np.random.default_rng(23)
+    D0, inv0, _, U0 = case(400, n, 1)
+    invs = np.stack([inv0 * (1.0 + 0.01 * q) for q in range(nmat)])
+    Us = np.stack([U0] * nmat)
+    counts = rng.integers(0, n + 1, nmat)
+    counts[:3] = [0, 1, n]
+    max_k = int(counts.max())
+    acc = np.zeros((nmat, max_k), dtype=np.int32)
+    lists = []
+    for q in range(nmat):
+        c = rng.permutation(n)[: counts[q]].astype(np.int64)
+        lists.append(c)
+        acc[q, : len(c)] = c
+    say(f"batched SM, two row blocks: {nmat} matrices of n = {n}, max_k = {max_k}")
+    inv_b = torch.from_numpy(invs).cuda()
+    r_b = blip.sm_update_batched(inv_b, torch.from_numpy(Us).cuda(), torch.from_numpy(acc).cuda(),
+                                 torch.from_numpy(counts.astype(np.int32)).cuda(), max_k)
+    torch.cuda.synchronize()
+    got_inv, got_r = to_np(inv_b), to_np(r_b)
+    for q in (0, 1, 2, 77, nmat - 1):
+        inv1 = torch.from_numpy(invs[q].copy()).cuda()
+        r1 = blip.sm_update(inv1, torch.from_numpy(U0).cuda(), lists[q])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got_inv[q], to_np(inv1), err_msg=f"matrix {q}")
+        np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
 
 
 def test_batched_padded_strides_and_untouched(blip):
