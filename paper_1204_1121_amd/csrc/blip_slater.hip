@@ -68,8 +68,9 @@ struct SmArgs {
     int colp[kSmChunk];  // electrons of the applied chunk, in move order
     int coln[kSmChunk];  // electrons of the next chunk
     int urow[kSmChunk];  // rows of u holding the next chunk's new orbitals
-    // Batched launches (blockIdx.z = matrix).  The chunk sizes and electron
-    // lists come from device memory; the offsets above are per matrix.
+    // Batched launches (one workgroup per matrix row block).  The chunk
+    // sizes and electron lists come from device memory; the offsets above
+    // are per matrix.
     int chunk;               // this launch applies chunk-1 and prepares chunk
     int max_k;               // moves per matrix are clamped to [0, max_k]
     const int* acc_cols;     // [nmat][acc_ld] electrons in move order
@@ -235,7 +236,8 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 // One launch: workgroup (x, y) applies chunk p to rows [16x, 16x+16) and
 // columns [y*tl, (y+1)*tl) of B, copies the moved rows of chunk n into Rn,
 // and writes its columns' share of V = B' U^T for chunk n to Pn[y].  In the
-// batched form blockIdx.z is the matrix and S^{-1} comes from sm_sinv_kernel.
+// batched form the workgroup index also selects the matrix, and S^{-1} comes
+// from sm_sinv_kernel.
 //
 // Both products run on the FP64 matrix cores, one 16 x 16 tile of B (16 rows,
 // 16 columns) at a time per wavefront.  Slot i of a tile (the matrix-core
@@ -281,7 +283,17 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     const double* Rp = a.Rp;
     double* Pn = a.Pn;
     double* Rn = a.Rn;
-    const int q = BATCHED ? (int)blockIdx.z : 0;
+    // The batched launch is one workgroup per (matrix, row block), its index
+    // mapped so that the row blocks of a matrix run on one XCD and share that
+    // XCD's L2 copy of the matrix's R and U (round-robin dispatch would give
+    // every XCD a copy).
+    int q = 0, rblk = (int)blockIdx.x;
+    if constexpr (BATCHED) {
+        const int nrb = (n + ROWS - 1) / ROWS;
+        const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+        q = t / nrb;
+        rblk = t - q * nrb;
+    }
     if constexpr (BATCHED) {
         sm_batched_counts(a, q, kp, kn);
         if (kp == 0 && kn == 0) return;   // nothing for this matrix in this launch
@@ -293,7 +305,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         Pn += wo;
         Rn += wo;
     }
-    const int i0 = blockIdx.x * ROWS;
+    const int i0 = rblk * ROWS;
 
     // index lists into LDS
     if constexpr (BATCHED) {
@@ -730,7 +742,7 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     // one workgroup per (row block, matrix); it walks the column tiles.  Two
     // 16-row blocks per workgroup while that still gives 4 workgroups per CU.
     const int rb = (n + 31) / 32 * (int64_t)nmat >= 4 * 256 ? 2 : 1;
-    const dim3 grid((unsigned)((n + 16 * rb - 1) / (16 * rb)), 1u, (unsigned)nmat);
+    const dim3 grid((unsigned)((n + 16 * rb - 1) / (16 * rb) * nmat));
 
     SmArgs a{};
     a.n = (int)n;

@@ -137,14 +137,17 @@ def test_orders_and_row_tilings(blip, n):
     check(blip, *case(100 + n, n, k), label="order")
 
 
-def test_padded_leading_dimensions(blip):
-    """inv and u with row strides above n (views into wider buffers)."""
+@pytest.mark.parametrize("ld,u_ld", [(80, 75), (71, 72)])
+def test_padded_leading_dimensions(blip, ld, u_ld):
+    """inv and u with row strides above n (views into wider buffers).  An
+    odd stride of inv, or a stride of u that is not a multiple of 4, makes
+    rows unaligned for 16-byte accesses: those rows take the scalar path."""
     D, inv_t, cols, U = case(4, 70, 45)
-    wide = np.full((70, 80), 7.0)
+    wide = np.full((70, ld), 7.0)
     wide[:, :70] = inv_t
     base = torch.from_numpy(wide).cuda()
     inv = base[:, :70]
-    Uw = np.full((70, 75), 3.0, dtype=np.float32)
+    Uw = np.full((70, u_ld), 3.0, dtype=np.float32)
     Uw[:, :70] = U
     u = torch.from_numpy(Uw).cuda()[:, :70]
     want_b, want_r = slater.sm_update(inv_t, U[cols].astype(np.float64), cols)
