@@ -677,6 +677,29 @@ def bench_paper_sizes(args, cache, leg=None):
     return rows
 
 
+def stream_copy_rate(nbytes=1 << 30, reps=10):
+    """Achievable HBM rate on this GPU as a second denominator: a 1 GiB
+    device-to-device copy (read plus write bytes over the event-timed copy),
+    after the kernel measurements so it does not disturb their caches."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del x, y
+    return 2 * nbytes / dt / 1e9
+
+
 def copy_probe(nbytes=1 << 30, reps=5):
     """A plain device copy of known size (calibrates rocprof byte counters)."""
     import torch
@@ -915,6 +938,13 @@ def main():
 
     if args.copy_probe:
         result["copy_probe"] = copy_probe()
+    else:
+        g = stream_copy_rate()
+        result["stream_copy"] = {"gbs": g, "bytes_per_copy": 2 << 30,
+                                 "tiled_kernel_frac_of_copy": achieved / g,
+                                 "tiled_kernel_traffic_frac_of_copy":
+                                     traffic / t_kernel / 1e9 / g if traffic else None}
+        log(f"stream copy {g:.0f} GB/s; tiled kernel at {achieved / g:.2f} of it (algorithmic bytes)")
 
     if leg is not None:
         log("timing the FP64 oracle on the host ...")
