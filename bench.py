@@ -483,10 +483,11 @@ def bench_vmc(args, table, spec):
     npos = W * 2 * n
     tr = wk.trial.view(npos, 3)
     phases = {
-        "ratios and values at the trial positions (one pass)":
-            lambda: table.ratio_values(tr, wk.inv.view(npos, n), out=(wk.ratio, wk.val),
-                                       stream=stream),
-        "local kinetic energy": wk.kinetic,
+        "ratios, values and Laplacian rows at the trial positions (one pass)":
+            lambda: table.ratio_values(tr, wk.inv.view(npos, n), lap=True, stream=stream,
+                                       out=(wk.ratio, wk.rg, wk.rl, wk.val, wk.lapt)),
+        "accepted Laplacian rows carried over": wk.carry_rows,
+        "local kinetic energy from the kept rows": wk.kinetic,
     }
     ph = {}
     for name, fn in phases.items():
@@ -499,6 +500,7 @@ def bench_vmc(args, table, spec):
         torch.cuda.synchronize()
         ph[name] = ev[0].elapsed_time(ev[1]) * 1e3 / steps
     ph["accept + inverse updates + propose (rest of the step)"] = t_step * 1e6 - sum(ph.values())
+    assert wk.lap_ok, "the timed steps must run from the kept Laplacian rows"
     res["throughput"] = {"walkers": W, "electrons_per_walker": 2 * n, "orbitals": n,
                          "us_per_step": t_step * 1e6, "walker_steps_per_s": W / t_step,
                          "electron_moves_per_s": W * 2 * n / t_step, "acceptance": acc,

@@ -269,16 +269,21 @@ BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
                              void* stream);
 
 /*
- * blip_eval_ratio_values -- the values-only blip_eval_ratio that also writes
- * the orbital values, val [npos][L] float, exactly as blip_eval writes them:
- * one pass gives a quasi-simultaneous step both its ratios and the new
- * orbital rows that the inverse update (blip_sm_update*) needs for the
- * accepted moves.  Same arguments and errors as blip_eval_ratio; val is
- * required, 4-byte aligned.
+ * blip_eval_ratio_values -- blip_eval_ratio that also writes the orbital
+ * values, val [npos][L] float, exactly as blip_eval writes them: one pass
+ * gives a quasi-simultaneous step both its ratios and the new orbital rows
+ * that the inverse update (blip_sm_update*) needs for the accepted moves.
+ * With grad_ratio, lap_ratio and lap (all three, or none) it is the full
+ * blip_eval_ratio and also writes the Laplacian rows, lap [npos][L] float as
+ * blip_eval writes them: the rows a caller keeps to evaluate the local
+ * kinetic energy of the configuration it accepts without evaluating the
+ * orbitals again (blip_qs_lap_ratios).  Same arguments and errors as
+ * blip_eval_ratio; val is required; val and lap 4-byte aligned.
  */
 BLIP_API int blip_eval_ratio_values(blip_table t, const double* pos, int64_t npos,
                                     const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
-                                    double* ratio, void* val, void* stream);
+                                    double* ratio, double* grad_ratio, double* lap_ratio,
+                                    void* val, void* lap, void* stream);
 
 /*
  * blip_eval_ratio_batched -- blip_eval_ratio for many walkers in one
@@ -404,6 +409,22 @@ BLIP_API size_t blip_sm_batched_workspace_size(int nmat, int64_t n);
  *   blip_eval_ratio at its current positions against its current inverses
  *   (sum_l lap psi_l(r_j) Dinv[l, j] = lap_j Psi_D / Psi_D), summed in a fixed
  *   order.  nwalk <= 65535.
+ *
+ * blip_qs_copy_rows -- for each (walker, spin) matrix q < nmat, the rows
+ *   q * n + acc_cols[q * acc_ld + i], i < acc_count[q], of src (row stride
+ *   src_ld floats) copied to the same rows of dst (stride dst_ld): len floats
+ *   each.  Carries the orbital rows evaluated at the trial positions (the
+ *   Laplacian rows of blip_eval_ratio_values) into the rows kept for the
+ *   current configuration, for the electrons blip_qs_accept accepted.
+ *   Counts are clamped to [0, n] and list entries to [0, n).  acc_ld >= n,
+ *   src_ld and dst_ld >= len; nmat <= 65535.
+ *
+ * blip_qs_lap_ratios -- lap_ratio[r] = sum_{l < len} lap[r][l] inv_rows[r][l]
+ *   (FP64 sums of the FP32 rows in a fixed order), r < nrows: with the
+ *   Laplacian rows of the orbitals at the current positions and the rows of
+ *   the current transposed inverses, the Laplacian ratios lap_j Psi_D /
+ *   Psi_D that blip_qs_kinetic sums, without evaluating the orbitals.
+ *   lap_ld, inv_ld >= len; lap 4-byte, inv_rows and lap_ratio 8-byte aligned.
  */
 BLIP_API int blip_qs_propose(int64_t npos, const double* pos, const double* eta, double* trial,
                              void* stream);
@@ -412,6 +433,12 @@ BLIP_API int blip_qs_accept(int nmat, int n, int j0, int j1, const double* ratio
                             int32_t* acc_cols, int64_t acc_ld, int32_t* acc_count, void* stream);
 BLIP_API int blip_qs_kinetic(int nwalk, int nel, const double* lap_ratio, double* e_kin,
                              void* stream);
+BLIP_API int blip_qs_copy_rows(int nmat, int n, int len, const int32_t* acc_cols, int64_t acc_ld,
+                              const int32_t* acc_count, const float* src, int64_t src_ld,
+                              float* dst, int64_t dst_ld, void* stream);
+BLIP_API int blip_qs_lap_ratios(int64_t nrows, int len, const float* lap, int64_t lap_ld,
+                               const double* inv_rows, int64_t inv_ld, double* lap_ratio,
+                               void* stream);
 
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */

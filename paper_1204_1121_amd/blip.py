@@ -84,7 +84,7 @@ def lib() -> ctypes.CDLL:
     L.blip_eval_ratio.restype = ci
     L.blip_eval_ratio.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
     L.blip_eval_ratio_values.restype = ci
-    L.blip_eval_ratio_values.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp]
+    L.blip_eval_ratio_values.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.blip_eval_ratio_batched.restype = ci
     L.blip_eval_ratio_batched.argtypes = [vp, vp, vp, ci, i64, vp, i64, vp, vp, vp, vp, vp,
                                           ctypes.c_size_t, vp]
@@ -104,6 +104,10 @@ def lib() -> ctypes.CDLL:
     L.blip_qs_accept.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, i64, vp, vp]
     L.blip_qs_kinetic.restype = ci
     L.blip_qs_kinetic.argtypes = [ci, ci, vp, vp, vp]
+    L.blip_qs_copy_rows.restype = ci
+    L.blip_qs_copy_rows.argtypes = [ci, ci, ci, vp, i64, vp, vp, i64, vp, i64, vp]
+    L.blip_qs_lap_ratios.restype = ci
+    L.blip_qs_lap_ratios.argtypes = [i64, ci, vp, i64, vp, i64, vp, vp]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -253,20 +257,30 @@ class Table:
         return r, g, l
 
     def ratio_values(self, pos: torch.Tensor, inv_rows: torch.Tensor, row_of=None, out=None,
-                     stream=None):
+                     lap: bool = False, stream=None):
         """blip_eval_ratio_values: the ratios and, in the same pass, the orbital
-        values.  Returns (ratio [npos] float64, val [npos, L] float32)."""
+        values.  Returns (ratio [npos] float64, val [npos, L] float32); with
+        lap=True (ratio, grad_ratio [npos, 3], lap_ratio [npos], val,
+        lap_rows [npos, L] float32)."""
         if inv_rows.dtype != torch.float64 or inv_rows.dim() != 2 or inv_rows.stride(1) != 1:
             raise ValueError("inv_rows must be a float64 CUDA matrix with unit column stride")
         npos = pos.shape[0]
+        dev = pos.device
         if out is None:
-            out = (torch.empty(npos, dtype=torch.float64, device=pos.device),
-                   torch.empty((npos, self.norb), dtype=torch.float32, device=pos.device))
-        r, v = out
+            out = (torch.empty(npos, dtype=torch.float64, device=dev),
+                   torch.empty((npos, self.norb), dtype=torch.float32, device=dev))
+            if lap:
+                out = (out[0], torch.empty((npos, 3), dtype=torch.float64, device=dev),
+                       torch.empty(npos, dtype=torch.float64, device=dev), out[1],
+                       torch.empty((npos, self.norb), dtype=torch.float32, device=dev))
+        if lap:
+            r, g, lr, v, lrow = out
+        else:
+            (r, v), g, lr, lrow = out, None, None, None
         check(lib().blip_eval_ratio_values(self.handle, _ptr(pos), npos, _ptr(inv_rows),
-                                           inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(v),
-                                           _stream_ptr(stream)))
-        return r, v
+                                           inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(g),
+                                           _ptr(lr), _ptr(v), _ptr(lrow), _stream_ptr(stream)))
+        return (r, g, lr, v, lrow) if lap else (r, v)
 
     def ratio_batched(self, pos, offsets, inv_rows, row_of=None, grad: bool = True, out=None,
                       workspace=None, capacity: int | None = None, stream=None):

@@ -723,10 +723,17 @@ tiled_kernel(const KArgs a)
                     for (int q = 0; q < NR; ++q) part[p][ch][q] = dot[q];
                 }
                 // optionally the values too: the new orbital rows that the
-                // inverse update after the accept/reject step needs
+                // inverse update after the accept/reject step needs; and the
+                // Laplacian rows, from which a caller keeps the kinetic
+                // energy of the configuration it accepts
                 if (a.val != nullptr && lane_ok)
                     store_elems<OE>(static_cast<ACC*>(a.val) + jo * W + e0, res[0], e0, W,
                                     a.vec_store != 0);
+                if constexpr (FULL) {
+                    if (a.lap != nullptr && lane_ok)
+                        store_elems<OE>(static_cast<ACC*>(a.lap) + jo * W + e0, res[4], e0, W,
+                                        a.vec_store != 0);
+                }
                 continue;   // nothing else is stored for this item
             }
             if (lane_ok) {

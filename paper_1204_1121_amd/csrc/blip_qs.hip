@@ -95,7 +95,52 @@ __global__ __launch_bounds__(kQsThreads) void qs_kinetic_kernel(int nel,
     if (tid == 0) e_kin[wk] = -0.5 * part[0];
 }
 
+// Rows of the accepted electrons copied from src to dst (both [nmat * n]
+// rows of len floats): workgroup (x, q) copies the listed rows x, x + gridDim.x,
+// ... of matrix q.  Entries of a list outside [0, n) are clamped, so a bad
+// list gives wrong rows, never an access out of bounds.
+__global__ __launch_bounds__(kQsThreads) void qs_copy_rows_kernel(
+    int n, int len, const int32_t* __restrict__ acc_cols, int64_t acc_ld,
+    const int32_t* __restrict__ acc_count, const float* __restrict__ src, int64_t src_ld,
+    float* __restrict__ dst, int64_t dst_ld)
+{
+    const int q = blockIdx.y;
+    int cnt = acc_count[q];
+    cnt = cnt < 0 ? 0 : (cnt > n ? n : cnt);
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        int j = acc_cols[(int64_t)q * acc_ld + i];
+        j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+        const int64_t r = (int64_t)q * n + j;
+        const float* sr = src + r * src_ld;
+        float* dr = dst + r * dst_ld;
+        for (int l = threadIdx.x; l < len; l += kQsThreads) dr[l] = sr[l];
+    }
+}
+
+// out[r] = sum_l lap[r][l] * inv[r][l] in FP64, one wavefront per row: lane
+// partial sums over a fixed stride, then a fixed butterfly (the same order on
+// every call).  With lap the Laplacian rows of the orbitals at electron r's
+// position and inv the matching row of the transposed inverse, out[r] is
+// lap_r D / D of the determinant.
+__global__ __launch_bounds__(kQsThreads) void qs_row_dots_kernel(
+    int64_t nrows, int len, const float* __restrict__ lap, int64_t lap_ld,
+    const double* __restrict__ inv, int64_t inv_ld, double* __restrict__ out)
+{
+    constexpr int kWaves = kQsThreads / 64;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); r < nrows;
+         r += (int64_t)gridDim.x * kWaves) {
+        const float* lr = lap + r * lap_ld;
+        const double* ir = inv + r * inv_ld;
+        double s = 0.0;
+        for (int l = lane; l < len; l += 64) s = fma((double)lr[l], ir[l], s);
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) out[r] = s;
+    }
+}
+
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 }  // namespace
 }  // namespace blip
@@ -157,6 +202,50 @@ BLIP_API int blip_qs_kinetic(int nwalk, int nel, const double* lap_ratio, double
                        static_cast<hipStream_t>(stream), nel, lap_ratio, e_kin);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? BLIP_OK : fail_hip(e, "qs_kinetic_kernel launch");
+}
+
+BLIP_API int blip_qs_copy_rows(int nmat, int n, int len, const int32_t* acc_cols, int64_t acc_ld,
+                              const int32_t* acc_count, const float* src, int64_t src_ld,
+                              float* dst, int64_t dst_ld, void* stream)
+{
+    if (nmat < 0 || nmat > 65535) return fail(BLIP_E_ARG, "nmat = %d outside [0, 65535]", nmat);
+    if (n < 1 || len < 0) return fail(BLIP_E_ARG, "n = %d must be >= 1 and len = %d >= 0", n, len);
+    if (acc_ld < n || src_ld < len || dst_ld < len)
+        return fail(BLIP_E_ARG, "acc_ld must be >= n and src_ld, dst_ld >= len");
+    if (nmat == 0 || len == 0) return BLIP_OK;
+    if (!acc_cols || !acc_count || !src || !dst)
+        return fail(BLIP_E_ARG, "acc_cols, acc_count, src and dst are required");
+    if (!aligned4(acc_cols) || !aligned4(acc_count) || !aligned4(src) || !aligned4(dst))
+        return fail(BLIP_E_ALIGN, "all arrays need 4-byte alignment");
+    const unsigned gx = (unsigned)std::min(n, 64);
+    hipLaunchKernelGGL(qs_copy_rows_kernel, dim3(gx, (unsigned)nmat), dim3(kQsThreads), 0,
+                       static_cast<hipStream_t>(stream), n, len, acc_cols, acc_ld, acc_count, src,
+                       src_ld, dst, dst_ld);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BLIP_OK : fail_hip(e, "qs_copy_rows_kernel launch");
+}
+
+BLIP_API int blip_qs_lap_ratios(int64_t nrows, int len, const float* lap, int64_t lap_ld,
+                               const double* inv_rows, int64_t inv_ld, double* lap_ratio,
+                               void* stream)
+{
+    if (nrows < 0 || len < 1)
+        return fail(BLIP_E_ARG, "nrows = %lld must be >= 0 and len = %d >= 1", (long long)nrows,
+                    len);
+    if (lap_ld < len || inv_ld < len)
+        return fail(BLIP_E_ARG, "lap_ld and inv_ld must be >= len (%d)", len);
+    if (nrows == 0) return BLIP_OK;
+    if (!lap || !inv_rows || !lap_ratio)
+        return fail(BLIP_E_ARG, "lap, inv_rows and lap_ratio are required");
+    if (!aligned4(lap) || !aligned8(inv_rows) || !aligned8(lap_ratio))
+        return fail(BLIP_E_ALIGN, "lap needs 4-byte, inv_rows and lap_ratio 8-byte alignment");
+    const int64_t wgs = (nrows + kQsThreads / 64 - 1) / (kQsThreads / 64);
+    const unsigned grid = (unsigned)std::min<int64_t>(wgs, 65536);
+    hipLaunchKernelGGL(qs_row_dots_kernel, dim3(grid), dim3(kQsThreads), 0,
+                       static_cast<hipStream_t>(stream), nrows, len, lap, lap_ld, inv_rows, inv_ld,
+                       lap_ratio);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BLIP_OK : fail_hip(e, "qs_row_dots_kernel launch");
 }
 
 }  // extern "C"

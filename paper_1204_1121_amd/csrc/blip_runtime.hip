@@ -518,18 +518,21 @@ BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
 
 BLIP_API int blip_eval_ratio_values(blip_table t, const double* pos, int64_t npos,
                                     const double* inv_rows, int64_t inv_ld, const int64_t* row_of,
-                                    double* ratio, void* val, void* stream)
+                                    double* ratio, double* gratio, double* lratio, void* val,
+                                    void* lap, void* stream)
 {
-    int rc = check_ratio_args(t, npos, pos, inv_rows, inv_ld, row_of, ratio, nullptr, nullptr);
+    if ((gratio == nullptr) != (lap == nullptr))
+        return fail(BLIP_E_ARG, "pass gratio, lratio and lap together, or none of them");
+    int rc = check_ratio_args(t, npos, pos, inv_rows, inv_ld, row_of, ratio, gratio, lratio);
     if (rc != BLIP_OK || npos == 0) return rc;
     if (val == nullptr) return fail(BLIP_E_ARG, "val is required");
-    if ((reinterpret_cast<uintptr_t>(val) & 3u) != 0)
-        return fail(BLIP_E_ALIGN, "val needs 4-byte alignment");
+    if ((reinterpret_cast<uintptr_t>(val) & 3u) != 0 || (reinterpret_cast<uintptr_t>(lap) & 3u) != 0)
+        return fail(BLIP_E_ALIGN, "val and lap need 4-byte alignment");
     int P = 0, OE = 0;
     rc = ratio_shape(t, MODE_BLOCK, npos, P, OE);
     if (rc != BLIP_OK) return rc;
-    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, nullptr, nullptr};
-    return launch_tiled(t, pos, npos, val, nullptr, nullptr, KIND_TILED, P, OE, nullptr, nullptr,
+    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, gratio, lratio};
+    return launch_tiled(t, pos, npos, val, nullptr, lap, KIND_TILED, P, OE, nullptr, nullptr,
                         nullptr, nullptr, 0, false, static_cast<hipStream_t>(stream), &ra);
 }
 

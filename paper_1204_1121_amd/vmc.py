@@ -7,13 +7,23 @@ quasi-simultaneous step (Sec. IV.A; the sequence of Sec. II.B) runs as:
 
   blip_qs_propose          trial = pos + eta for every electron
   blip_eval_ratio_values   in one pass: each move's ratio against the old
-                           configuration and psi_l at every trial position
-                           (the new rows)
+                           configuration, psi_l at every trial position (the
+                           new rows) and lap psi_l there
   blip_qs_accept           uniform < ratio^2; accepted positions copied and
                            listed per (walker, spin) in electron order
   blip_sm_update_batched   the inverses brought up to date for those moves
-  blip_eval_ratio + blip_qs_kinetic   the local kinetic energy per walker,
-                           -1/2 sum_j lap_j Psi / Psi at the new positions
+  blip_qs_copy_rows        the accepted electrons' Laplacian rows carried into
+                           the rows kept for the current configuration
+  blip_qs_lap_ratios +     the local kinetic energy per walker,
+  blip_qs_kinetic          -1/2 sum_j lap_j Psi / Psi at the new positions,
+                           from the kept rows and the new inverses
+
+The walker keeps the Laplacian rows of the orbitals at its current positions
+(lap psi_l(r_j), [2n, n] float32 per walker), so the kinetic energy after a
+step costs a pass over those rows and the inverses instead of a second
+evaluation of the orbitals.  A step run without the energy leaves the rows
+stale; the next kinetic energy then evaluates them afresh
+(blip_eval_ratio_values at the current positions).
 
 Random numbers are the caller's (eta Gaussian, uniform in [0, 1)), so a step
 can be replayed against the FP64 oracle.  Everything above runs in this
@@ -57,6 +67,9 @@ class Walkers:
         self.acc_count = torch.zeros(2 * W, dtype=torch.int32, device=dev)
         self.seq = torch.empty((2 * W, n), dtype=torch.float64, device=dev)
         self.e_kin = torch.empty(W, dtype=torch.float64, device=dev)
+        self.lap = torch.empty((npos, n), dtype=torch.float32, device=dev)    # current positions
+        self.lapt = torch.empty((npos, n), dtype=torch.float32, device=dev)   # trial positions
+        self.lap_ok = False   # whether self.lap holds the rows of the current positions
         nbytes = _b.lib().blip_sm_batched_workspace_size(2 * W, n)
         self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
         if inv_t is None:
@@ -81,29 +94,54 @@ class Walkers:
         W, n, s = self.W, self.n, self.stream
         npos = W * 2 * n
         L = _b.lib()
+        keep = energy and self.lap_ok   # carry the kept Laplacian rows forward
         eta = eta.contiguous()
         uniform = uniform.contiguous()
         self._call(L.blip_qs_propose(npos, _b._ptr(self.pos), _b._ptr(eta), _b._ptr(self.trial),
                                      _b._stream_ptr(s)))
         tr = self.trial.view(npos, 3)
-        self.t.ratio_values(tr, self.inv.view(npos, n), out=(self.ratio, self.val), stream=s)
+        if keep:
+            self.t.ratio_values(tr, self.inv.view(npos, n), lap=True, stream=s,
+                                out=(self.ratio, self.rg, self.rl, self.val, self.lapt))
+        else:
+            self.t.ratio_values(tr, self.inv.view(npos, n), out=(self.ratio, self.val), stream=s)
         self._call(L.blip_qs_accept(2 * W, n, j0, n if j1 is None else j1, _b._ptr(self.ratio),
                                     _b._ptr(uniform), _b._ptr(self.trial), _b._ptr(self.pos),
                                     _b._ptr(self.acc_cols), n, _b._ptr(self.acc_count),
                                     _b._stream_ptr(s)))
         _b.sm_update_batched(self.inv, self.val.view(2 * W, n, n), self.acc_cols,
                              self.acc_count, n, ratios=self.seq, workspace=self.ws, stream=s)
+        if keep:
+            self.carry_rows()
+        else:
+            self.lap_ok = False
         e = None
         if energy:
             e = self.kinetic()
         return self.acc_count, e
 
+    def carry_rows(self):
+        """The accepted electrons' Laplacian rows (at their trial positions,
+        now their positions) into the kept rows."""
+        W, n, s = self.W, self.n, self.stream
+        self._call(_b.lib().blip_qs_copy_rows(2 * W, n, n, _b._ptr(self.acc_cols), n,
+                                              _b._ptr(self.acc_count), _b._ptr(self.lapt), n,
+                                              _b._ptr(self.lap), n, _b._stream_ptr(s)))
+
     def kinetic(self):
-        """Local kinetic energy of every walker at its current positions."""
+        """Local kinetic energy of every walker at its current positions:
+        from the kept Laplacian rows when they are current, else from a fresh
+        evaluation at the current positions (which also refreshes them)."""
         W, n, s = self.W, self.n, self.stream
         npos = W * 2 * n
-        self.t.ratio(self.pos.view(npos, 3), self.inv.view(npos, n), grad=True,
-                     out=(self.ratio, self.rg, self.rl), stream=s)
+        if self.lap_ok:
+            self._call(_b.lib().blip_qs_lap_ratios(npos, n, _b._ptr(self.lap), n,
+                                                   _b._ptr(self.inv), n, _b._ptr(self.rl),
+                                                   _b._stream_ptr(s)))
+        else:
+            self.t.ratio_values(self.pos.view(npos, 3), self.inv.view(npos, n), lap=True,
+                                stream=s, out=(self.ratio, self.rg, self.rl, self.val, self.lap))
+            self.lap_ok = True
         self._call(_b.lib().blip_qs_kinetic(W, 2 * n, _b._ptr(self.rl), _b._ptr(self.e_kin),
                                            _b._stream_ptr(s)))
         return self.e_kin

@@ -171,7 +171,7 @@ def test_sm_update_batched_argument_errors(blip):
 
 
 def test_qs_helpers_argument_errors(blip):
-    """blip_qs_propose / blip_qs_accept / blip_qs_kinetic reject bad sizes,
+    """blip_qs_propose / accept / kinetic / copy_rows / lap_ratios reject bad sizes,
     ranges and alignment on the host (fake pointers, never dereferenced)."""
     L = blip.lib()
     dev = ctypes.c_void_p(0x10000)
@@ -196,3 +196,26 @@ def test_qs_helpers_argument_errors(blip):
     assert L.blip_qs_kinetic(2, 0, dev, dev, None) == -1
     assert L.blip_qs_kinetic(2, 8, odd, dev, None) == -5
     assert L.blip_qs_kinetic(0, 8, None, None, None) == 0
+
+    def copy(nmat=2, n=8, ln=8, ld=8, sld=8, dld=8, src=dev, cols=dev):
+        return L.blip_qs_copy_rows(nmat, n, ln, cols, ld, dev, src, sld, dev, dld, None)
+
+    assert copy(nmat=-1) == -1 and copy(nmat=70000) == -1
+    assert copy(n=0) == -1 and copy(ln=-1) == -1
+    assert copy(ld=7) == -1 and copy(sld=7) == -1 and copy(dld=7) == -1
+    assert copy(src=None) == -1
+    assert copy(src=ctypes.c_void_p(0x10002)) == -5
+    assert copy(nmat=0) == 0 and copy(ln=0) == 0
+    assert L.blip_qs_lap_ratios(-1, 8, dev, 8, dev, 8, dev, None) == -1
+    assert L.blip_qs_lap_ratios(4, 0, dev, 8, dev, 8, dev, None) == -1
+    assert L.blip_qs_lap_ratios(4, 8, dev, 7, dev, 8, dev, None) == -1
+    assert L.blip_qs_lap_ratios(4, 8, dev, 8, dev, 7, dev, None) == -1
+    assert L.blip_qs_lap_ratios(4, 8, None, 8, dev, 8, dev, None) == -1
+    assert L.blip_qs_lap_ratios(4, 8, dev, 8, odd, 8, dev, None) == -5
+    assert L.blip_qs_lap_ratios(0, 8, None, 8, None, 8, None, None) == 0
+    # blip_eval_ratio_values takes gradient and Laplacian ratios and rows
+    # together or not at all (checked before the table handle)
+    assert L.blip_eval_ratio_values(None, dev, 4, dev, 8, None, dev, dev, dev, dev, None,
+                                    None) == -1
+    assert L.blip_eval_ratio_values(None, dev, 4, dev, 8, None, dev, None, None, dev, dev,
+                                    None) == -1

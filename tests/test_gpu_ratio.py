@@ -180,4 +180,15 @@ def test_ratio_values_one_pass(blip, storage):
     np.testing.assert_array_equal(to_np(r2), want_r)
     np.testing.assert_array_equal(to_np(v_off), want_v)
     assert to_np(buf)[0] == 7.0
+    # the full form: ratios with gradient and Laplacian, the values and the
+    # Laplacian rows, bit for bit those of blip_eval_ratio and blip_eval
+    wr, wg, wl = (to_np(x) for x in t.ratio(p, inv, grad=True))
+    _, _, wlap = t.eval(p, grad=True)
+    r3, g3, l3, v3, lap3 = t.ratio_values(p, inv, lap=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(r3), wr)
+    np.testing.assert_array_equal(to_np(g3), wg)
+    np.testing.assert_array_equal(to_np(l3), wl)
+    np.testing.assert_array_equal(to_np(v3), want_v)
+    np.testing.assert_array_equal(to_np(lap3), to_np(wlap))
     t.free()

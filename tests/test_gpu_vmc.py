@@ -107,3 +107,52 @@ def test_setup_inverse_and_kinetic_of_fresh_walkers(setup):
     for w in range(W):
         ek = ovmc.local_kinetic(A, NG, coef, pos[w], inv[w])
         assert abs(e[w] - ek) <= cond_bar(coef, pos[w]) * lap_scale(coef, pos[w], inv[w])
+
+
+def test_kept_laplacian_rows_and_helpers(setup):
+    """Energies from the kept Laplacian rows equal a fresh evaluation at the
+    same positions and inverses (FP64 sums of the same FP32 rows, in another
+    order); blip_qs_copy_rows copies exactly the listed rows;
+    blip_qs_lap_ratios equals an FP64 dot of the rows."""
+    blip, vmc, t, coef, pos, inv, rng = setup
+    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(inv.copy()).cuda())
+    for _ in range(3):
+        eta = torch.from_numpy(rng.normal(0, 0.5, pos.shape)).cuda()
+        uni = torch.from_numpy(rng.uniform(0, 1, (W, 2 * L))).cuda()
+        _, e = wk.step(eta, uni)
+    assert wk.lap_ok
+    kept = to_np(e).copy()
+    kept_rows = to_np(wk.lap).copy()
+    wk.lap_ok = False
+    fresh = to_np(wk.kinetic())
+    say(f"kept-row energies {kept} against fresh {fresh}")
+    np.testing.assert_allclose(kept, fresh, rtol=1e-12, atol=1e-12 * np.abs(fresh).max())
+    np.testing.assert_array_equal(kept_rows, to_np(wk.lap))   # same FP32 rows either way
+    # the helpers alone
+    nmat, n = 2 * W, L
+    src = torch.from_numpy(rng.standard_normal((nmat * n, n)).astype(np.float32)).cuda()
+    dst0 = rng.standard_normal((nmat * n, n)).astype(np.float32)
+    dst = torch.from_numpy(dst0.copy()).cuda()
+    counts = rng.integers(0, n + 1, nmat).astype(np.int32)
+    cols = np.zeros((nmat, n), dtype=np.int32)
+    want = dst0.copy()
+    for q in range(nmat):
+        c = np.sort(rng.permutation(n)[: counts[q]])
+        cols[q, : len(c)] = c
+        want[q * n + c] = to_np(src)[q * n + c]
+    lib = blip.lib()
+    dcols, dcounts = torch.from_numpy(cols).cuda(), torch.from_numpy(counts).cuda()
+    assert lib.blip_qs_copy_rows(nmat, n, n, dcols.data_ptr(), n, dcounts.data_ptr(),
+                                 src.data_ptr(), n, dst.data_ptr(), n, None) == 0
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(dst), want)
+    a = rng.standard_normal((37, 50)).astype(np.float32)
+    b = rng.standard_normal((37, 61))
+    out = torch.empty(37, dtype=torch.float64, device="cuda")
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    assert lib.blip_qs_lap_ratios(37, 50, ta.data_ptr(), 50, tb.data_ptr(), 61,
+                                  out.data_ptr(), None) == 0
+    torch.cuda.synchronize()
+    want = np.einsum("rl,rl->r", a.astype(np.float64), b[:, :50])
+    scale = np.einsum("rl,rl->r", np.abs(a.astype(np.float64)), np.abs(b[:, :50]))
+    assert np.all(np.abs(to_np(out) - want) <= 64 * np.finfo(np.float64).eps * scale)
