@@ -23,12 +23,15 @@
 // accepted moves takes ceil(K/32)+1 launches, and each launch reads and
 // writes B once.
 //
+// The two products of a launch (the rank-k update and V of the next chunk)
+// run on the FP64 matrix cores, 16 x 16 tiles of B per wavefront.
+//
 // Two entry points share these kernels.  blip_sm_update serves one matrix
 // and is latency-bound: every workgroup eliminates S itself, which costs less
 // than another launch.  blip_sm_update_batched serves many matrices (walkers
 // and spins): a workgroup per matrix eliminates S once (sm_sinv_kernel), and
-// the chunk kernel's workgroups, 16 rows each, read S^{-1}.  Both run the
-// same arithmetic in the same order.
+// the chunk kernel's workgroups, 16 or 32 rows each, read S^{-1}.  Both run
+// the same arithmetic in the same order, so their results agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -233,10 +236,11 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
         a.ratio[(int64_t)q * a.ratio_ld + (int64_t)(a.chunk - 1) * kSmChunk + tid] = piv[tid];
 }
 
-// One launch: workgroup (x, y) applies chunk p to rows [16x, 16x+16) and
-// columns [y*tl, (y+1)*tl) of B, copies the moved rows of chunk n into Rn,
-// and writes its columns' share of V = B' U^T for chunk n to Pn[y].  In the
-// batched form the workgroup index also selects the matrix, and S^{-1} comes
+// One launch: single-matrix workgroup (x, y) applies chunk p to rows
+// [16x, 16x+16) and columns [y*tl, (y+1)*tl) of B, copies the moved rows of
+// chunk n into Rn, and writes its columns' share of V = B' U^T for chunk n to
+// Pn[y].  In the batched form the workgroup index selects the matrix and a
+// block of 16 RB rows, the workgroup walks all column tiles, and S^{-1} comes
 // from sm_sinv_kernel.
 //
 // Both products run on the FP64 matrix cores, one 16 x 16 tile of B (16 rows,
