@@ -322,6 +322,38 @@ def bench_batched(table, spec, args, nbatch=4):
     return res
 
 
+def bench_block_sizes(table, spec, stream, sizes=(1, 8, 64, 256, 1536), reps=200):
+    """Move blocks of 1 to 1,536 positions on the 768-orbital table: kernel
+    time from per-launch event pairs (median, p99) over blocks rotated as in
+    the main figure, and end-to-end latency, host submit to completion, of
+    one launch at a time (synchronised before and after)."""
+    import torch
+    from paper_1204_1121_amd import workloads as wl
+    L = spec.norb
+    rows = []
+    for B in sizes:
+        blocks = [torch.from_numpy(wl.move_block(spec, B, block=b)).cuda() for b in range(NROT)]
+        out = table.alloc_outputs(B)
+        calls = {id(b): table.bind(b, out) for b in blocks}
+        _, durs = time_launches(lambda b: calls[id(b)](), blocks, reps, 20, stream)
+        e2e = []
+        for i in range(50):
+            call = calls[id(blocks[i % NROT])]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            e2e.append(time.perf_counter() - t0)
+        med = float(np.median(durs))
+        rows.append({"npos": B, "kernel_us_median": med * 1e6,
+                     "kernel_us_p99": float(np.percentile(durs, 99)) * 1e6,
+                     "e2e_us_median": float(np.median(e2e)) * 1e6,
+                     "evals_per_s": B * L / med, "shape": list(table.get_shape(B))})
+        log(f"block of {B}: kernel {med * 1e6:.1f} us (p99 {rows[-1]['kernel_us_p99']:.1f}), "
+            f"submit-to-completion {rows[-1]['e2e_us_median']:.1f} us")
+    return rows
+
+
 def bench_serving(args):
     """Three resident systems (the 768-orbital table; 48^3 x 256; 96x96x64 x
     1024), requests of 1..1536 positions (log-uniform) arriving by Poisson
@@ -724,6 +756,8 @@ def main():
     ap.add_argument("--npos", type=int, default=1536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="skip the block sizes 1 .. 1,536 (kernel time and submit-to-completion)")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache measurement (profiling runs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-walker batch")
@@ -843,6 +877,12 @@ def main():
         "bytes_per_launch": {"algorithmic": b_alg_mean, "gather_no_reuse": b_gather,
                              "distinct_rows": float(np.mean(U))},
     }
+
+    if not args.no_blocks:
+        try:
+            result["block_sizes"] = bench_block_sizes(table, spec, stream)
+        except Exception as e:
+            result["block_sizes"] = {"error": f"{type(e).__name__}: {e}"}
 
     if not args.no_plain:
         def plain_step(pos):
