@@ -54,6 +54,7 @@ struct KArgs {
     int ntiles;              // ceil(npos / P)
     int vec_store;           // 1 if W % o == 0 (whole-vector stores allowed)
     int chunk_major;         // item order within a tile: chunk-major if 1
+    int chunk_split;         // non-persistent launch: workgroups per tile, each a share of its chunks (0, 1: one)
     double G[9];             // A^{-1}
     double M[9];             // M_cd = n_d G_cd  (d t_d / d r_c)
     double g[6];             // g_11, g_22, g_33, g_12, g_13, g_23 (g = M^T M)
@@ -632,14 +633,22 @@ tiled_kernel(const KArgs a)
             nr[2] = rp[2];
         }
     };
-    int tile;
+    // A launch with too few tiles to fill the chip gives each tile CS
+    // workgroups (chunk_split), each taking a contiguous share of its orbital
+    // chunks, so that a small block is not one long chain of row loads per
+    // wavefront.  (Not with the ratio epilogue, which sums a position's
+    // chunks inside one workgroup.)
+    const int CS = (!persist && !RATIO && a.chunk_split > 1) ? a.chunk_split : 1;
+    int tile, share = 0;
     if (persist) {
         if (threadIdx.x == 0) s_next = atomicAdd(&a.xcd_next[x], 1);
         __syncthreads();
         tile = xcd_begin + s_next;
         __syncthreads();   // all threads have read s_next
     } else {
-        tile = xcd_tile(blockIdx.x, ntiles);
+        const int u = xcd_tile(blockIdx.x, ntiles * CS);
+        tile = u / CS;
+        share = u - tile * CS;
     }
     fetch(tile);
 
@@ -656,7 +665,8 @@ tiled_kernel(const KArgs a)
             fetch(next);
         }
 
-        const int items = np * C;
+        const int cb = share * C / CS, nc = (share + 1) * C / CS - cb;   // this workgroup's chunks
+        const int items = np * nc;
         for (int item = wave; item < items; item += nwaves) {
             // chunk-major order: the wavefronts of a workgroup work on the
             // same orbital chunk of neighbouring positions at the same time,
@@ -666,9 +676,10 @@ tiled_kernel(const KArgs a)
                 ch = item / np;
                 p = item - ch * np;
             } else {
-                p = item / C;
-                ch = item - p * C;
+                p = item / nc;
+                ch = item - p * nc;
             }
+            ch += cb;
             const int64_t slot = j0 + p;
             const int64_t jo = a.perm ? (int64_t)a.perm[slot] : slot;
             const int e0 = (ch * kWave + lane) * OE;

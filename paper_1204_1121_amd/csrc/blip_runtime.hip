@@ -240,6 +240,20 @@ int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* v
         return BLIP_OK;
     }
     make_cfg(t, kind, P, OE, grad != nullptr, dev_count ? grid : ntiles, c, a);
+    if (!dev_count) {
+        // fewer tiles than two workgroups per CU, each with little work (a
+        // latency chain of row loads, not a stream): split each tile's chunks
+        // over up to C workgroups (the arithmetic of every element is
+        // unchanged).  Tiles with many items keep one workgroup, which wraps
+        // their positions once.
+        const int64_t want = 2 * (int64_t)std::max(1, t->ncu);
+        if (ntiles < want && a.chunks > 1 && P * a.chunks <= 16) {
+            const int cs = (int)std::min<int64_t>(a.chunks, (want + ntiles - 1) / ntiles);
+            a.chunk_split = cs;
+            c.grid = (int)(ntiles * cs);
+            c.nwaves = std::min(4, std::max(1, (int)(P * ((a.chunks + cs - 1) / cs))));
+        }
+    }
     hipError_t e = dispatch(t, a, c, s);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return BLIP_OK;
