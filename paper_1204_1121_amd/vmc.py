@@ -37,9 +37,6 @@ D_{w,s}^{-1} (the layout blip_eval_ratio and blip_sm_update read).
 """
 from __future__ import annotations
 
-import ctypes
-
-import numpy as np
 import torch
 
 from . import blip as _b

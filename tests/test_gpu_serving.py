@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_1204_1121_amd import workloads as wl
-from paper_1204_1121_amd.serve import DONE, GpuBackend, Server, ServeRequest
+from paper_1204_1121_amd.serve import GpuBackend, Server, ServeRequest
 from tests.gpu_util import group_errors, say, to_np
 
 pytestmark = pytest.mark.gpu

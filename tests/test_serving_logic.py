@@ -1,7 +1,6 @@
 """Serving scheduler logic on the CPU: a fake backend that evaluates with the
 FP64 oracle and finishes launches on a fake clock."""
 import numpy as np
-import pytest
 
 import oracle
 from paper_1204_1121_amd.serve import (DONE, FAILED, REJECTED, TIMEOUT, Server,
