@@ -261,6 +261,38 @@ def test_batched_two_row_blocks_equals_single_bitwise(blip):
         np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
 
 
+@pytest.mark.parametrize("n", [1, 2, 4096])
+def test_batched_extreme_orders(blip, n):
+    """The smallest orders and the largest accepted one (four column tiles,
+    up to 128 chunks): two matrices, all and half of the electrons moved,
+    bit for bit the single-matrix update."""
+    counts = [n, n // 2]
+    rng = np.random.default_rng(500 + n)
+    invs, Us, lists = [], [], []
+    for q in range(2):
+        D, inv_t, _, U = case(510 + n + q, n, 1)
+        invs.append(inv_t)
+        Us.append(U)
+        lists.append(rng.permutation(n)[: counts[q]].astype(np.int64))
+    max_k = max(counts)
+    acc = np.zeros((2, max(max_k, 1)), dtype=np.int32)
+    for q, c in enumerate(lists):
+        acc[q, : len(c)] = c
+    say(f"batched SM, order {n}: counts {counts}")
+    inv_b = torch.from_numpy(np.stack(invs)).cuda()
+    r_b = blip.sm_update_batched(inv_b, torch.from_numpy(np.stack(Us)).cuda(),
+                                 torch.from_numpy(acc).cuda(),
+                                 torch.tensor(counts, dtype=torch.int32, device="cuda"), max_k)
+    torch.cuda.synchronize()
+    got_inv, got_r = to_np(inv_b), to_np(r_b)
+    for q in range(2):
+        inv1 = torch.from_numpy(invs[q]).cuda()
+        r1 = blip.sm_update(inv1, torch.from_numpy(Us[q]).cuda(), lists[q])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got_inv[q], to_np(inv1), err_msg=f"matrix {q}")
+        np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
+
+
 def test_batched_padded_strides_and_untouched(blip):
     """Matrices with padded rows inside a wider buffer, u with extra rows:
     columns past n and matrices with no moves are left as they were."""
