@@ -322,11 +322,12 @@ def bench_batched(table, spec, args, nbatch=4):
     return res
 
 
-def bench_block_sizes(table, spec, stream, sizes=(1, 8, 64, 256, 1536), reps=200):
+def bench_block_sizes(table, spec, stream, cache, args, sizes=(1, 8, 64, 256, 1536), reps=200):
     """Move blocks of 1 to 1,536 positions on the 768-orbital table: kernel
     time from per-launch event pairs (median, p99) over blocks rotated as in
     the main figure, and end-to-end latency, host submit to completion, of
-    one launch at a time (synchronised before and after)."""
+    one launch at a time (synchronised before and after).  Each size runs the
+    shape cached for its size bucket, autotuned on these blocks if none is."""
     import torch
     from paper_1204_1121_amd import workloads as wl
     L = spec.norb
@@ -334,6 +335,9 @@ def bench_block_sizes(table, spec, stream, sizes=(1, 8, 64, 256, 1536), reps=200
     for B in sizes:
         blocks = [torch.from_numpy(wl.move_block(spec, B, block=b)).cuda() for b in range(NROT)]
         out = table.alloc_outputs(B)
+        if args.retune or not cache.apply(table, B):
+            best, _ = table.autotune(torch.cat(blocks).contiguous(), out, rotate=NROT)
+            cache.put(table, B, False, best, note=f"blip_autotune rotate={NROT}")
         calls = {id(b): table.bind(b, out) for b in blocks}
         _, durs = time_launches(lambda b: calls[id(b)](), blocks, reps, 20, stream)
         e2e = []
@@ -880,7 +884,9 @@ def main():
 
     if not args.no_blocks:
         try:
-            result["block_sizes"] = bench_block_sizes(table, spec, stream)
+            result["block_sizes"] = bench_block_sizes(table, spec, stream, cache, args)
+            if args.save_tuning:
+                cache.save(args.save_tuning)
         except Exception as e:
             result["block_sizes"] = {"error": f"{type(e).__name__}: {e}"}
 
