@@ -136,6 +136,25 @@ class CpuBaselineLeg:
         except OSError:
             pass
 
+    def replay_qs(self, lattice, n_grid, coef, start, etas, unis):
+        """The oracle's own FP64 chain of quasi-simultaneous steps from the
+        same start with the same random numbers: the double-precision
+        counterpart of a GPU chain (its inverses from its own FP64 Slater
+        matrices).  start [W, 2n, 3]; etas [K, W, 2n, 3]; unis [K, W, 2n].
+        Returns (kinetic energies [K, W], accept masks [K, W, 2n])."""
+        from oracle import vmc as ovmc
+        K, W = etas.shape[0], start.shape[0]
+        E = np.empty((K, W))
+        acc = np.zeros((K, W, start.shape[1]), dtype=bool)
+        for w in range(W):
+            pos = start[w].copy()
+            D = ovmc.slater_matrices(lattice, n_grid, coef, pos)
+            inv = np.stack([np.linalg.inv(D[0]).T, np.linalg.inv(D[1]).T])
+            for k in range(K):
+                pos, inv, acc[k, w], _, _, E[k, w] = ovmc.qs_step(lattice, n_grid, coef, pos, inv,
+                                                                  etas[k, w], unis[k, w])
+        return E, acc
+
     def blocks(self, spec, coef, npos, budget_s=12.0):
         """FP64 oracle on a bounded sample of the same workload, all host
         cores: whole move blocks of the benchmark's shape, as many as fit
@@ -474,7 +493,7 @@ def bench_precision(args, real_coef, real_spec, cache, leg=None):
     return out
 
 
-def bench_vmc(args, table, spec):
+def bench_vmc(args, table, spec, leg=None):
     """Quasi-simultaneous Monte Carlo steps on the device.
 
     Throughput: 16 walkers of the TiO2 system (2 x 768 electrons each, the
@@ -555,6 +574,8 @@ def bench_vmc(args, table, spec):
     chains = {"quasi_simultaneous": vmc.Walkers(ts, start.clone(), stream=stream),
               "configuration_by_configuration": vmc.Walkers(ts, start.clone(), stream=stream)}
     nequil, nsample, sig = 200, 1000, 0.3
+    nrec, wrec = (100, 8) if leg is not None else (0, 0)   # steps replayed on the oracle
+    rec = {"eta": [], "uni": [], "e": [], "acc": []}
     stats = {}
     for name, wk in chains.items():
         gs = torch.Generator(device="cuda").manual_seed(wl.SEED_BASE + 13)   # same draws
@@ -569,7 +590,14 @@ def bench_vmc(args, table, spec):
                                     generator=gs)
             uni = torch.rand((Ws, 2 * Ls), dtype=torch.float64, device="cuda", generator=gs)
             if name == "quasi_simultaneous":
+                if it < nrec:
+                    before = wk.pos[:wrec].clone()
                 cnt, e = wk.step(eta, uni)
+                if it < nrec:
+                    rec["eta"].append(eta[:wrec].cpu().numpy())
+                    rec["uni"].append(uni[:wrec].cpu().numpy())
+                    rec["e"].append(e[:wrec].cpu().numpy())
+                    rec["acc"].append((wk.pos[:wrec] != before).any(dim=2).cpu().numpy())
                 seq = torch.where(lanes < wk.acc_count[:, None], wk.seq.abs(),
                                   torch.full_like(wk.seq, float("inf")))
                 seq_min = torch.minimum(seq_min, seq.min())
@@ -598,6 +626,32 @@ def bench_vmc(args, table, spec):
     stats["setup"] = (f"{Ws} walkers x {2 * Ls} electrons, {Ls} orbitals on a {ng} grid, "
                       f"sigma {sig} bohr, {nequil} equilibration + {nsample} sampled steps, the "
                       "same random draws for both chains; stderr over walker means")
+    if leg is not None:
+        # the paper's single- against double-precision comparison (Table
+        # energy_eval), on this system: the GPU chain (FP32 orbitals, FP64
+        # inverses) against the oracle's FP64 chain with the same draws
+        t0 = time.perf_counter()
+        E_o, acc_o = leg.replay_qs(A, ng, coef, start[:wrec].cpu().numpy(),
+                                   np.stack(rec["eta"]), np.stack(rec["uni"]))
+        E_g, acc_g = np.stack(rec["e"]), np.stack(rec["acc"])
+        same = (acc_g == acc_o).all(axis=2)                       # [K, W]
+        # steps up to each walker's first differing decision (chains agree there)
+        upto = np.where(same.all(axis=0), nrec, np.argmin(same, axis=0))
+        mask = np.arange(nrec)[:, None] < upto[None, :]
+        dev = np.abs(E_g - E_o)[mask]
+        stats["double_precision_replay"] = {
+            "walkers": wrec, "steps": nrec,
+            "walkers_with_a_differing_decision": int((upto < nrec).sum()),
+            "first_differing_step": [int(u) if u < nrec else None for u in upto],
+            "max_abs_energy_deviation_hartree": float(dev.max()) if dev.size else None,
+            "max_rel_energy_deviation": float((dev / np.abs(E_o[mask])).max()) if dev.size else None,
+            "mean_kinetic_gpu": float(E_g[mask].mean()) if dev.size else None,
+            "mean_kinetic_oracle_fp64": float(E_o[mask].mean()) if dev.size else None,
+            "oracle_seconds": time.perf_counter() - t0}
+        dr = stats["double_precision_replay"]
+        log(f"vmc replay on the FP64 oracle: {nrec} steps x {wrec} walkers, "
+            f"{dr['walkers_with_a_differing_decision']} walkers with a differing decision, "
+            f"max |dE| {dr['max_abs_energy_deviation_hartree']} Ha")
     res["statistics"] = stats
     log(f"vmc statistics: Q.S. E_kin {q['mean_kinetic_hartree']:.2f} +- {q['stderr']:.2f} "
         f"(median walker {q['median_walker_mean']:.2f}, max |E_L| {q['max_abs_local_energy']:.3g}, "
@@ -959,7 +1013,7 @@ def main():
 
     if not args.no_vmc:
         try:
-            result["vmc"] = bench_vmc(args, table, spec)
+            result["vmc"] = bench_vmc(args, table, spec, leg)
         except Exception as e:
             result["vmc"] = {"error": f"{type(e).__name__}: {e}"}
 
