@@ -324,7 +324,7 @@ struct NOut { static constexpr int value = !FULL ? 1 : (ORTHO ? 5 : 10); };
 // The outer m1 loop is kept rolled so that at most 16 row loads (one
 // 4x4 slab of the stencil) are in flight per wavefront; this bounds the
 // register footprint and lets several wavefronts share each SIMD.
-template <class E, int OE, bool FULL, bool ORTHO, class ACC>
+template <class E, int OE, bool FULL, bool ORTHO, class ACC, bool ALL4 = false>
 __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int voff,
                                             int64_t row_bytes, int n3,
                                             const PosPrep<ACC>& pp,
@@ -363,22 +363,10 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
                 load_elems_buf<E, OE, ACC>(r, voff, off3[m3], x[m2][m3]);
         }
     };
-    ACC xn[4][4][OE];
-    load_slab(0, xn);
-
-#pragma unroll 1
-    for (int m1 = 0; m1 < 4; ++m1) {
+    auto sum_slab = [&](int m1, const ACC (&x)[4][4][OE]) {
         ACC w1[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) w1[k] = uniform_f(pp.w[0][k][m1]);
-        ACC x[4][4][OE];
-#pragma unroll
-        for (int m2 = 0; m2 < 4; ++m2)
-#pragma unroll
-            for (int m3 = 0; m3 < 4; ++m3)
-#pragma unroll
-                for (int e = 0; e < OE; ++e) x[m2][m3][e] = xn[m2][m3][e];
-        if (m1 < 3) load_slab(m1 + 1, xn);
 
         // middle-level sums over m2
         constexpr int NB = !FULL ? 1 : (ORTHO ? 4 : 6);
@@ -446,6 +434,31 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
                     out[9][e] = fma_(w0, b[5][e], out[9][e]);   // d23
                 }
             }
+        }
+    };
+
+    if constexpr (ALL4) {
+        // small launches: all 64 rows in flight at once (one load latency
+        // per item instead of four), summed in the same order
+        ACC xa[4][4][4][OE];
+#pragma unroll
+        for (int m1 = 0; m1 < 4; ++m1) load_slab(m1, xa[m1]);
+#pragma unroll
+        for (int m1 = 0; m1 < 4; ++m1) sum_slab(m1, xa[m1]);
+    } else {
+        ACC xn[4][4][OE];
+        load_slab(0, xn);
+#pragma unroll 1
+        for (int m1 = 0; m1 < 4; ++m1) {
+            ACC x[4][4][OE];
+#pragma unroll
+            for (int m2 = 0; m2 < 4; ++m2)
+#pragma unroll
+                for (int m3 = 0; m3 < 4; ++m3)
+#pragma unroll
+                    for (int e = 0; e < OE; ++e) x[m2][m3][e] = xn[m2][m3][e];
+            if (m1 < 3) load_slab(m1 + 1, xn);
+            sum_slab(m1, x);
         }
     }
 }
@@ -583,7 +596,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 constexpr int kRatioTile = 16;     // largest P with the ratio epilogue
 constexpr int kRatioChunks = 16;   // largest number of orbital chunks with it
 
-template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC, bool RATIO = false>
+template <class E, int OE, bool FULL, bool ORTHO, bool BLOCH, class ACC, bool RATIO = false,
+          bool ALL4 = false>
 __global__ void __launch_bounds__(kMaxThreads)
 tiled_kernel(const KArgs a)
 {
@@ -688,8 +702,8 @@ tiled_kernel(const KArgs a)
             // discarded) so the loop below stays free of divergence.
             const int e_ld = lane_ok ? e0 : ch * kWave * OE;
             ACC acc[NO][OE];
-            gather_item<E, OE, FULL, ORTHO, ACC>(a.coef, e_ld * E::bytes, a.row_bytes, a.n3,
-                                                 prep[p], acc);
+            gather_item<E, OE, FULL, ORTHO, ACC, ALL4>(a.coef, e_ld * E::bytes, a.row_bytes, a.n3,
+                                                       prep[p], acc);
             ACC res[5][OE];
             finish_cartesian<FULL, ORTHO, ACC, OE>(a, acc, res);
             if constexpr (__is_same(E, F16)) {

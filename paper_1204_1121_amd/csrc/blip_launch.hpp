@@ -18,6 +18,7 @@ struct Cfg {
     bool full;     // gradient and Laplacian too
     bool ortho;    // diagonal metric folded into the weights
     bool bloch;    // complex table with a k-point
+    bool all4;     // small launch: every row of an item in flight at once (o = 1)
 };
 
 template <class E>
@@ -80,6 +81,13 @@ hipError_t go_tiled(const KArgs& a, const Cfg& c, hipStream_t s)
         // the Bloch factor needs whole complex pairs per lane and FP32 outputs
         return hipErrorInvalidValue;
     } else {
+        if constexpr (OE == 1 && __is_same(ACC, float)) {
+            if (c.all4) {
+                hipLaunchKernelGGL((tiled_kernel<E, OE, FULL, ORTHO, BLOCH, ACC, false, true>),
+                                   dim3(c.grid), dim3(kWave * c.nwaves), 0, s, a);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((tiled_kernel<E, OE, FULL, ORTHO, BLOCH, ACC>), dim3(c.grid),
                            dim3(kWave * c.nwaves), 0, s, a);
         return hipGetLastError();

@@ -200,6 +200,7 @@ void make_cfg(const blip_table_s* t, int kind, int P, int OE, bool full, int64_t
     c.full = full;
     c.ortho = t->ortho;
     c.bloch = t->bloch;
+    c.all4 = false;
 }
 
 int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* val, void* grad,
@@ -252,6 +253,7 @@ int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* v
             a.chunk_split = cs;
             c.grid = (int)(ntiles * cs);
             c.nwaves = std::min(4, std::max(1, (int)(P * ((a.chunks + cs - 1) / cs))));
+            c.all4 = (OE == 1);   // and every row of an item in flight at once
         }
     }
     hipError_t e = dispatch(t, a, c, s);
