@@ -493,7 +493,34 @@ def bench_precision(args, real_coef, real_spec, cache, leg=None):
     return out
 
 
-def bench_vmc(args, table, spec, leg=None):
+def tune_ratio_pass(wk, table, npos, stream):
+    """The sorted ratio pass's launch shape for this step size: every
+    (P, o) timed over ten passes at the walkers' current trial positions, the
+    fastest kept on the table.  Only the shape changes: the values and
+    Laplacian rows are the same at every shape, the ratios the same up to
+    FP64 rounding."""
+    import torch
+    tr = wk.trial.view(npos, 3)
+    outs = (wk.ratio, wk.rg, wk.rl, wk.val, wk.lapt)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    found = []
+    for P in (1, 2, 4, 8, 16):
+        for o in (1, 2, 4):
+            table.set_shape(npos, P, o, batched=True)
+            wk.ratio_values(tr, outs)
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for _ in range(10):
+                wk.ratio_values(tr, outs)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            found.append({"tile_pos": P, "vec": o, "us": ev[0].elapsed_time(ev[1]) * 100.0})
+    best = min(found, key=lambda e: e["us"])
+    table.set_shape(npos, best["tile_pos"], best["vec"], batched=True)
+    return best
+
+
+def bench_vmc(args, table, spec, leg=None, cache=None):
     """Quasi-simultaneous Monte Carlo steps on the device.
 
     Throughput: 16 walkers of the TiO2 system (2 x 768 electrons each, the
@@ -525,6 +552,20 @@ def bench_vmc(args, table, spec, leg=None):
     for i in range(3):
         wk.step(etas[i % 4], unis[i % 4])
     torch.cuda.synchronize()
+    npos = W * 2 * n
+    shape = None
+    if wk.sorted:
+        # the sorted ratio pass's shape: from the tuning cache, else measured
+        if cache is not None and not args.retune and cache.apply(table, npos, batched=True,
+                                                                 ratio=True):
+            shape = dict(cache.get(table, npos, True, ratio=True), **{"from": "tuning cache"})
+        else:
+            shape = dict(tune_ratio_pass(wk, table, npos, stream), **{"from": "measured"})
+            if cache is not None:
+                cache.put(table, npos, True, shape, ratio=True,
+                          note=f"ratio pass sweep, {W}-walker step")
+        log(f"vmc: sorted ratio pass, shape P={shape['tile_pos']} o={shape['vec']} "
+            f"({shape['from']})")
     steps = 10
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record(stream)
@@ -535,12 +576,10 @@ def bench_vmc(args, table, spec, leg=None):
     t_step = ev[0].elapsed_time(ev[1]) * 1e-3 / steps
     acc = float(wk.acc_count.sum().item()) / (W * 2 * n)
     # phases, each timed alone over the same step inputs
-    npos = W * 2 * n
     tr = wk.trial.view(npos, 3)
     phases = {
         "ratios, values and Laplacian rows at the trial positions (one pass)":
-            lambda: table.ratio_values(tr, wk.inv.view(npos, n), lap=True, stream=stream,
-                                       out=(wk.ratio, wk.rg, wk.rl, wk.val, wk.lapt)),
+            lambda: wk.ratio_values(tr, (wk.ratio, wk.rg, wk.rl, wk.val, wk.lapt)),
         "accepted Laplacian rows carried over": wk.carry_rows,
         "local kinetic energy from the kept rows": wk.kinetic,
     }
@@ -559,7 +598,9 @@ def bench_vmc(args, table, spec, leg=None):
     res["throughput"] = {"walkers": W, "electrons_per_walker": 2 * n, "orbitals": n,
                          "us_per_step": t_step * 1e6, "walker_steps_per_s": W / t_step,
                          "electron_moves_per_s": W * 2 * n / t_step, "acceptance": acc,
-                         "sigma_bohr": sigma, "phases_us": ph}
+                         "sigma_bohr": sigma, "phases_us": ph,
+                         "ratio_pass": ({"launch": "sorted persistent", "shape": shape}
+                                        if wk.sorted else {"launch": "block"})}
     del wk
     log(f"vmc: {t_step * 1e6:.0f} us per quasi-simultaneous step of {W} walkers x {2 * n} "
         f"electrons ({W / t_step:.0f} walker-steps/s, acceptance {acc:.2f})")
@@ -1013,7 +1054,9 @@ def main():
 
     if not args.no_vmc:
         try:
-            result["vmc"] = bench_vmc(args, table, spec, leg)
+            result["vmc"] = bench_vmc(args, table, spec, leg, cache)
+            if args.save_tuning:
+                cache.save(args.save_tuning)
         except Exception as e:
             result["vmc"] = {"error": f"{type(e).__name__}: {e}"}
 

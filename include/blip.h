@@ -300,6 +300,30 @@ BLIP_API int blip_eval_ratio_batched(blip_table t, const double* pos, const int6
                                      size_t workspace_bytes, void* stream);
 
 /*
+ * blip_eval_ratio_values_batched -- blip_eval_ratio_values in the sorted
+ * persistent launch of blip_eval_ratio_batched: the moved electrons of many
+ * walkers (both spins) evaluated as one set of positions (Eq. (11.12.23.1)
+ * makes every trial move independent), in spatial order so that moves of
+ * different walkers near the same grid sites share the rows they read.
+ * val [capacity][L] float is required; grad_ratio, lap_ratio and lap
+ * [capacity][L] float go together or not at all, as in
+ * blip_eval_ratio_values.  Rows j < offsets[nw] are written at index j (the
+ * caller's order).  The values and Laplacian rows equal blip_eval's bit for
+ * bit; the ratios equal blip_eval_ratio_values' when both run with the same
+ * orbitals per lane (blip_set_shape), as they sum the same per-lane products
+ * in the same order.  Same workspace and errors as blip_eval_ratio_batched,
+ * plus BLIP_E_ARG without val and BLIP_E_ALIGN for val or lap not 4-byte
+ * aligned.  Asynchronous on the stream; the sort and the evaluation make five
+ * launches, capturable in a graph.
+ */
+BLIP_API int blip_eval_ratio_values_batched(blip_table t, const double* pos,
+                                            const int64_t* offsets, int nw, int64_t capacity,
+                                            const double* inv_rows, int64_t inv_ld,
+                                            const int64_t* row_of, double* ratio, double* gratio,
+                                            double* lratio, void* val, void* lap, void* workspace,
+                                            size_t workspace_bytes, void* stream);
+
+/*
  * blip_sm_update -- bring the inverse Slater matrix up to date after the
  * accepted moves of a step (Sec. VI.D; the Slater matrix of Eq. (5)):
  * the moves are applied in the given order, each as the Sherman-Morrison

@@ -88,6 +88,9 @@ def lib() -> ctypes.CDLL:
     L.blip_eval_ratio_batched.restype = ci
     L.blip_eval_ratio_batched.argtypes = [vp, vp, vp, ci, i64, vp, i64, vp, vp, vp, vp, vp,
                                           ctypes.c_size_t, vp]
+    L.blip_eval_ratio_values_batched.restype = ci
+    L.blip_eval_ratio_values_batched.argtypes = [vp, vp, vp, ci, i64, vp, i64, vp, vp, vp, vp,
+                                                 vp, vp, vp, ctypes.c_size_t, vp]
     L.blip_sm_update.restype = ci
     L.blip_sm_update.argtypes = [i64, vp, i64, vp, i64, i64, vp, vp, i64, vp, vp,
                                  ctypes.c_size_t, vp]
@@ -300,6 +303,37 @@ class Table:
                                             _ptr(l), _ptr(workspace), workspace.numel(),
                                             _stream_ptr(stream)))
         return r, g, l
+
+    def ratio_values_batched(self, pos, offsets, inv_rows, row_of=None, out=None, lap=False,
+                             workspace=None, capacity: int | None = None, stream=None):
+        """blip_eval_ratio_values_batched: ratio_values for concatenated
+        walker blocks in one sorted persistent launch.  Returns (ratio, val),
+        or with lap=True (ratio, grad_ratio, lap_ratio, val, lap_rows), with
+        ``capacity`` rows."""
+        if inv_rows.dtype != torch.float64 or inv_rows.dim() != 2 or inv_rows.stride(1) != 1:
+            raise ValueError("inv_rows must be a float64 CUDA matrix with unit column stride")
+        if offsets.dtype != torch.int64 or not offsets.is_cuda:
+            raise ValueError("offsets must be a CUDA int64 tensor [nw+1]")
+        cap = pos.shape[0] if capacity is None else int(capacity)
+        dev = pos.device
+        if out is None:
+            out = (torch.empty(cap, dtype=torch.float64, device=dev),
+                   torch.empty((cap, self.norb), dtype=torch.float32, device=dev))
+            if lap:
+                out = (out[0], torch.empty((cap, 3), dtype=torch.float64, device=dev),
+                       torch.empty(cap, dtype=torch.float64, device=dev), out[1],
+                       torch.empty((cap, self.norb), dtype=torch.float32, device=dev))
+        if lap:
+            r, g, lr, v, lrow = out
+        else:
+            (r, v), g, lr, lrow = out, None, None, None
+        if workspace is None:
+            workspace = self.workspace(cap, dev)
+        check(lib().blip_eval_ratio_values_batched(
+            self.handle, _ptr(pos), _ptr(offsets), int(offsets.shape[0]) - 1, cap,
+            _ptr(inv_rows), inv_rows.stride(0), _ptr(row_of), _ptr(r), _ptr(g), _ptr(lr),
+            _ptr(v), _ptr(lrow), _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+        return (r, g, lr, v, lrow) if lap else (r, v)
 
     # -- batched walker blocks -------------------------------------------
 

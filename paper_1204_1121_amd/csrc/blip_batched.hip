@@ -279,6 +279,34 @@ static int batched_shape(const blip_table_s* t, int64_t capacity, int& P, int& O
     return BLIP_OK;
 }
 
+// The sorted persistent launch with the acceptance-ratio epilogue; val and
+// lap (NULL: not stored) receive the orbital values and Laplacian rows.
+static int ratio_batched(blip_table t, const double* pos, const int64_t* offsets, int nw,
+                         int64_t capacity, const double* inv_rows, int64_t inv_ld,
+                         const int64_t* row_of, double* ratio, double* gratio, double* lratio,
+                         void* val, void* lap, void* workspace, size_t workspace_bytes,
+                         hipStream_t s)
+{
+    int rc = check_ratio_args(t, capacity, pos, inv_rows, inv_ld, row_of, ratio, gratio, lratio);
+    if (rc != BLIP_OK) return rc;
+    if (nw < 0) return fail(BLIP_E_ARG, "nw must be >= 0 (got %d)", nw);
+    if (nw == 0 || capacity == 0) return BLIP_OK;
+    if (offsets == nullptr || (reinterpret_cast<uintptr_t>(offsets) & 7u) != 0)
+        return fail(BLIP_E_ARG, "offsets must be non-NULL and 8-byte aligned");
+    const SortLayout L = sort_layout(t, capacity);
+    if (workspace == nullptr || workspace_bytes < L.total)
+        return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", L.total,
+                    workspace_bytes);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+        return fail(BLIP_E_ALIGN, "workspace must be 256-byte aligned");
+    int P = 0, OE = 0;
+    rc = ratio_shape(t, MODE_BATCHED, capacity, P, OE);
+    if (rc != BLIP_OK) return rc;
+    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, gratio, lratio};
+    return enqueue_batched(t, pos, offsets, nw, capacity, val, nullptr, lap, workspace, P, OE, s,
+                           &ra);
+}
+
 }  // namespace blip
 
 struct blip_plan_s {
@@ -322,25 +350,29 @@ BLIP_API int blip_eval_ratio_batched(blip_table t, const double* pos, const int6
                                      double* grad_ratio, double* lap_ratio, void* workspace,
                                      size_t workspace_bytes, void* stream)
 {
-    int rc = check_ratio_args(t, capacity, pos, inv_rows, inv_ld, row_of, ratio, grad_ratio,
-                              lap_ratio);
-    if (rc != BLIP_OK) return rc;
-    if (nw < 0) return fail(BLIP_E_ARG, "nw must be >= 0 (got %d)", nw);
-    if (nw == 0 || capacity == 0) return BLIP_OK;
-    if (offsets == nullptr || (reinterpret_cast<uintptr_t>(offsets) & 7u) != 0)
-        return fail(BLIP_E_ARG, "offsets must be non-NULL and 8-byte aligned");
-    const SortLayout L = sort_layout(t, capacity);
-    if (workspace == nullptr || workspace_bytes < L.total)
-        return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", L.total,
-                    workspace_bytes);
-    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
-        return fail(BLIP_E_ALIGN, "workspace must be 256-byte aligned");
-    int P = 0, OE = 0;
-    rc = ratio_shape(t, MODE_BATCHED, capacity, P, OE);
-    if (rc != BLIP_OK) return rc;
-    const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, grad_ratio, lap_ratio};
-    return enqueue_batched(t, pos, offsets, nw, capacity, nullptr, nullptr, nullptr, workspace, P,
-                           OE, static_cast<hipStream_t>(stream), &ra);
+    return ratio_batched(t, pos, offsets, nw, capacity, inv_rows, inv_ld, row_of, ratio,
+                         grad_ratio, lap_ratio, nullptr, nullptr, workspace, workspace_bytes,
+                         static_cast<hipStream_t>(stream));
+}
+
+BLIP_API int blip_eval_ratio_values_batched(blip_table t, const double* pos,
+                                            const int64_t* offsets, int nw, int64_t capacity,
+                                            const double* inv_rows, int64_t inv_ld,
+                                            const int64_t* row_of, double* ratio, double* gratio,
+                                            double* lratio, void* val, void* lap, void* workspace,
+                                            size_t workspace_bytes, void* stream)
+{
+    if ((gratio == nullptr) != (lap == nullptr))
+        return fail(BLIP_E_ARG, "pass gratio, lratio and lap together, or none of them");
+    if (capacity > 0 && nw > 0) {
+        if (val == nullptr) return fail(BLIP_E_ARG, "val is required");
+        if ((reinterpret_cast<uintptr_t>(val) & 3u) != 0 ||
+            (reinterpret_cast<uintptr_t>(lap) & 3u) != 0)
+            return fail(BLIP_E_ALIGN, "val and lap need 4-byte alignment");
+    }
+    return ratio_batched(t, pos, offsets, nw, capacity, inv_rows, inv_ld, row_of, ratio, gratio,
+                         lratio, val, lap, workspace, workspace_bytes,
+                         static_cast<hipStream_t>(stream));
 }
 
 BLIP_API int blip_plan_create(blip_table t, const double* pos, const int64_t* offsets, int nw,

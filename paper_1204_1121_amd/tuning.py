@@ -5,9 +5,11 @@ per lane o) on the caller's buffers; this module keeps the winners in a JSON
 file keyed by architecture, storage dtype, orbital count, grid, path (single
 block or batched), outputs (with derivatives, or values only) and the
 power-of-two size bucket, and restores them into a table with
-blip_set_shape, so a run does not need to re-tune.  A table holds one shape
-per size bucket, so a caller that uses one table for both output modes
-restores the mode it runs.
+blip_set_shape, so a run does not need to re-tune.  Shapes measured for the
+acceptance-ratio pass (the ratio epilogue with the values and Laplacian rows)
+are kept under their own path.  A table holds one shape per size bucket, so a
+caller that uses one table for several output modes restores the mode it
+runs.
 """
 from __future__ import annotations
 
@@ -25,10 +27,11 @@ def bucket(npos: int) -> int:
     return lo
 
 
-def key(table, npos: int, batched: bool, values_only: bool = False,
+def key(table, npos: int, batched: bool, values_only: bool = False, ratio: bool = False,
         arch: str = "gfx950") -> str:
     n1, n2, n3 = table.n
-    path = ("batched" if batched else "block") + ("-values" if values_only else "")
+    path = (("batched" if batched else "block") + ("-values" if values_only else "")
+            + ("-ratio" if ratio else ""))
     return f"{arch}/{table.storage}/L{table.norb}/{n1}x{n2}x{n3}/{path}/{bucket(npos)}"
 
 
@@ -40,20 +43,22 @@ class TuneCache:
             with open(path) as f:
                 self.entries = json.load(f)
 
-    def get(self, table, npos: int, batched: bool = False, values_only: bool = False):
-        return self.entries.get(key(table, npos, batched, values_only))
+    def get(self, table, npos: int, batched: bool = False, values_only: bool = False,
+            ratio: bool = False):
+        return self.entries.get(key(table, npos, batched, values_only, ratio))
 
     def put(self, table, npos: int, batched: bool, best: dict, note: str = "",
-            values_only: bool = False) -> None:
+            values_only: bool = False, ratio: bool = False) -> None:
         e = {"tile_pos": int(best["tile_pos"]), "vec": int(best["vec"]),
              "us": float(best["us"])}
         if note:
             e["note"] = note
-        self.entries[key(table, npos, batched, values_only)] = e
+        self.entries[key(table, npos, batched, values_only, ratio)] = e
 
-    def apply(self, table, npos: int, batched: bool = False, values_only: bool = False) -> bool:
+    def apply(self, table, npos: int, batched: bool = False, values_only: bool = False,
+              ratio: bool = False) -> bool:
         """Set the cached shape on the table; False if none is cached."""
-        e = self.get(table, npos, batched, values_only)
+        e = self.get(table, npos, batched, values_only, ratio)
         if e is None:
             return False
         table.set_shape(npos, e["tile_pos"], e["vec"], batched=batched)

@@ -7,8 +7,11 @@ quasi-simultaneous step (Sec. IV.A; the sequence of Sec. II.B) runs as:
 
   blip_qs_propose          trial = pos + eta for every electron
   blip_eval_ratio_values   in one pass: each move's ratio against the old
-                           configuration, psi_l at every trial position (the
-                           new rows) and lap psi_l there
+  (_batched)               configuration, psi_l at every trial position (the
+                           new rows) and lap psi_l there; for many moves the
+                           sorted persistent launch, in which the moves of all
+                           walkers that fall near the same grid sites share
+                           the table rows they read
   blip_qs_accept           uniform < ratio^2; accepted positions copied and
                            listed per (walker, spin) in electron order
   blip_sm_update_batched   the inverses brought up to date for those moves
@@ -41,10 +44,15 @@ import torch
 
 from . import blip as _b
 
+# From this many trial moves per step on, the ratio pass runs as one sorted
+# persistent launch over all walkers; below it the sort's five small launches
+# cost more than the row sharing saves.
+SORT_MIN_MOVES = 4096
+
 
 class Walkers:
     def __init__(self, table: "_b.Table", pos: torch.Tensor, inv_t: torch.Tensor | None = None,
-                 stream=None):
+                 stream=None, sort_moves: bool | None = None):
         if table.complex:
             raise ValueError("the synthetic system uses real orbitals")
         W, ne, three = pos.shape
@@ -69,6 +77,10 @@ class Walkers:
         self.lap_ok = False   # whether self.lap holds the rows of the current positions
         nbytes = _b.lib().blip_sm_batched_workspace_size(2 * W, n)
         self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        self.sorted = npos >= SORT_MIN_MOVES if sort_moves is None else bool(sort_moves)
+        if self.sorted:
+            self.off = torch.tensor([0, npos], dtype=torch.int64, device=dev)
+            self.rws = table.workspace(npos, dev)
         if inv_t is None:
             self.t.eval(self.pos.view(npos, 3), grad=False, out=(self.val, None, None),
                         stream=stream)
@@ -80,6 +92,19 @@ class Walkers:
 
     def _call(self, rc):
         _b.check(rc)
+
+    def ratio_values(self, pos_flat: torch.Tensor, out: tuple):
+        """Ratios against the current inverses, the orbital values and, with
+        five outputs, the gradient and Laplacian ratios and the Laplacian
+        rows, at pos_flat [2Wn, 3] (electron j uses inverse row j)."""
+        npos, n, s = self.W * 2 * self.n, self.n, self.stream
+        lap = len(out) == 5
+        inv = self.inv.view(npos, n)
+        if self.sorted:
+            self.t.ratio_values_batched(pos_flat, self.off, inv, out=out, lap=lap,
+                                        workspace=self.rws, stream=s)
+        else:
+            self.t.ratio_values(pos_flat, inv, out=out, lap=lap, stream=s)
 
     def step(self, eta: torch.Tensor, uniform: torch.Tensor, energy: bool = True,
              j0: int = 0, j1: int | None = None):
@@ -98,10 +123,9 @@ class Walkers:
                                      _b._stream_ptr(s)))
         tr = self.trial.view(npos, 3)
         if keep:
-            self.t.ratio_values(tr, self.inv.view(npos, n), lap=True, stream=s,
-                                out=(self.ratio, self.rg, self.rl, self.val, self.lapt))
+            self.ratio_values(tr, (self.ratio, self.rg, self.rl, self.val, self.lapt))
         else:
-            self.t.ratio_values(tr, self.inv.view(npos, n), out=(self.ratio, self.val), stream=s)
+            self.ratio_values(tr, (self.ratio, self.val))
         self._call(L.blip_qs_accept(2 * W, n, j0, n if j1 is None else j1, _b._ptr(self.ratio),
                                     _b._ptr(uniform), _b._ptr(self.trial), _b._ptr(self.pos),
                                     _b._ptr(self.acc_cols), n, _b._ptr(self.acc_count),
@@ -136,8 +160,8 @@ class Walkers:
                                                    _b._ptr(self.inv), n, _b._ptr(self.rl),
                                                    _b._stream_ptr(s)))
         else:
-            self.t.ratio_values(self.pos.view(npos, 3), self.inv.view(npos, n), lap=True,
-                                stream=s, out=(self.ratio, self.rg, self.rl, self.val, self.lap))
+            self.ratio_values(self.pos.view(npos, 3),
+                              (self.ratio, self.rg, self.rl, self.val, self.lap))
             self.lap_ok = True
         self._call(_b.lib().blip_qs_kinetic(W, 2 * n, _b._ptr(self.rl), _b._ptr(self.e_kin),
                                            _b._stream_ptr(s)))

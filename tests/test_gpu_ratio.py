@@ -192,3 +192,63 @@ def test_ratio_values_one_pass(blip, storage):
     np.testing.assert_array_equal(to_np(v3), want_v)
     np.testing.assert_array_equal(to_np(lap3), to_np(wlap))
     t.free()
+
+
+@pytest.mark.parametrize("o", [1, 2])
+def test_ratio_values_batched(blip, o):
+    """blip_eval_ratio_values_batched: ragged walker blocks (one of them
+    empty) in one sorted persistent launch.  Values and Laplacian rows equal
+    blip_eval's bit for bit; with the block launch held to the same orbitals
+    per lane, the ratios equal blip_eval_ratio_values' bit for bit; rows past
+    offsets[nw] are not written; and the ratios agree with the oracle."""
+    rng = np.random.default_rng(29)
+    n = (12, 11, 10)
+    L = 100
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    t = blip.Table(SKEW, n, c, "f32")
+    nwalk = 6
+    invs, blocks, rows = [], [], []
+    for w in range(nwalk):
+        R, inv_rows, moves = setup(SKEW, n, c, L, 300 + w)
+        k = 0 if w == 2 else int(rng.integers(1, L + 1))
+        who = rng.choice(L, k, replace=False)
+        invs.append(inv_rows)
+        blocks.append(moves[who])
+        rows.append(w * L + who)
+    pos = np.concatenate(blocks)
+    total = pos.shape[0]
+    cap = total + 5
+    off = np.zeros(nwalk + 1, dtype=np.int64)
+    off[1:] = np.cumsum([b.shape[0] for b in blocks])
+    allinv_np = np.concatenate(invs)
+    allrows = np.concatenate(rows).astype(np.int64)
+    allinv = torch.from_numpy(allinv_np).cuda()
+    row_of = torch.from_numpy(np.concatenate([allrows, np.zeros(5, np.int64)])).cuda()
+    p = torch.from_numpy(np.concatenate([pos, np.zeros((5, 3))])).cuda()
+    offs = torch.from_numpy(off).cuda()
+    t.set_shape(total, 8, o)
+    t.set_shape(cap, 8, o, batched=True)
+    say(f"batched ratio values: {nwalk} walkers, {total} moves, L={L}, o={o}")
+    out = (torch.full((cap,), 7.0, dtype=torch.float64, device="cuda"),
+           torch.full((cap, 3), 7.0, dtype=torch.float64, device="cuda"),
+           torch.full((cap,), 7.0, dtype=torch.float64, device="cuda"),
+           torch.full((cap, L), 7.0, dtype=torch.float32, device="cuda"),
+           torch.full((cap, L), 7.0, dtype=torch.float32, device="cuda"))
+    r, g, lr, v, lap = t.ratio_values_batched(p, offs, allinv, row_of=row_of, out=out, lap=True)
+    rb, gb, lrb, vb, lapb = t.ratio_values(p[:total], allinv, row_of=row_of[:total], lap=True)
+    ev, _, elap = t.eval(p[:total])
+    torch.cuda.synchronize()
+    for x in out:
+        assert bool((x[total:] == 7.0).all()), "a row past offsets[nw] was written"
+    assert torch.equal(v[:total], ev) and torch.equal(lap[:total], elap)
+    assert torch.equal(r[:total], rb) and torch.equal(g[:total], gb)
+    assert torch.equal(lr[:total], lrb)
+    # the values-only form gives the same ratios and values
+    r2, v2 = t.ratio_values_batched(p, offs, allinv, row_of=row_of, capacity=cap)
+    torch.cuda.synchronize()
+    assert torch.equal(r2[:total], r[:total]) and torch.equal(v2[:total], v[:total])
+    ref = oracle.ratio(SKEW, n, c, pos, allinv_np, allrows)
+    vals = oracle.evaluate(SKEW, n, c, pos)
+    check_ratio({"ratio": to_np(r[:total]), "grad": to_np(g[:total]), "lap": to_np(lr[:total])},
+                ref, vals, allinv_np, allrows, 1e-5, "batched values vs oracle")
+    t.free()

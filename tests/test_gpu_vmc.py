@@ -53,9 +53,12 @@ def lap_scale(coef, pos_w, inv_w):
     return 0.5 * (np.abs(o["lap"][:L] * inv_w[0]).sum() + np.abs(o["lap"][L:] * inv_w[1]).sum())
 
 
-def test_qs_steps_match_oracle(setup):
+@pytest.mark.parametrize("sort_moves", [False, True])
+def test_qs_steps_match_oracle(setup, sort_moves):
     blip, vmc, t, coef, pos, inv, rng = setup
-    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(inv.copy()).cuda())
+    wk = vmc.Walkers(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(inv.copy()).cuda(),
+                     sort_moves=sort_moves)
+    assert wk.sorted == sort_moves
     cur_pos, cur_inv = pos.copy(), inv.copy()
     for step in range(3):
         eta = rng.normal(0, 0.5, pos.shape)
@@ -156,3 +159,44 @@ def test_kept_laplacian_rows_and_helpers(setup):
     want = np.einsum("rl,rl->r", a.astype(np.float64), b[:, :50])
     scale = np.einsum("rl,rl->r", np.abs(a.astype(np.float64)), np.abs(b[:, :50]))
     assert np.all(np.abs(to_np(out) - want) <= 64 * np.finfo(np.float64).eps * scale)
+
+
+def test_sorted_ratio_pass_same_chain(setup):
+    """40 walkers of 2 x 64 electrons (5,120 moves a step, enough for the
+    sorted persistent ratio pass by default): three steps with the sorted pass
+    and with the block pass, from the same start and random numbers, take the
+    same decisions (none within 1e-9 of a tie), reach the same positions and
+    inverses bit for bit (the same FP32 orbital rows, the same updates), and
+    energies equal to 1e-12."""
+    blip, vmc = setup[0], setup[1]
+    rng = np.random.default_rng(zlib.crc32(b"gpu-vmc-sorted"))
+    n, nw = 64, 40
+    coef = rng.uniform(-1, 1, NG + (n,)).astype(np.float32)
+    t = blip.Table(A, NG, coef, "f32")
+    pos = torch.from_numpy(rng.uniform(0, 1, (nw, 2 * n, 3)) @ A).cuda()
+    a = vmc.Walkers(t, pos.clone())
+    b = vmc.Walkers(t, pos.clone(), inv_t=a.inv.clone(), sort_moves=False)
+    assert a.sorted and not b.sorted
+    say(f"sorted vs block ratio pass: {nw} walkers x {2 * n} electrons")
+    # kept rows current from the start, so every step runs the full ratio
+    # pass and leaves the trial moves' ratios in place for the tie check
+    ka, kb = a.kinetic(), b.kinetic()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(to_np(ka), to_np(kb), rtol=1e-12,
+                               atol=1e-12 * float(np.abs(to_np(kb)).max()))
+    for step in range(3):
+        eta = torch.from_numpy(rng.normal(0, 0.3, (nw, 2 * n, 3))).cuda()
+        uni = torch.from_numpy(rng.uniform(0, 1, (nw, 2 * n))).cuda()
+        ca, ea = a.step(eta, uni)
+        cb, eb = b.step(eta, uni)
+        torch.cuda.synchronize()
+        r2 = to_np(b.ratio) ** 2
+        # the two passes' ratios differ by FP64 rounding only (different
+        # orbitals per lane are summed in another order)
+        assert np.min(np.abs(to_np(uni).ravel() - r2)) > 1e-9, "a decision is within rounding"
+        assert torch.equal(ca, cb), step
+        assert torch.equal(a.pos, b.pos) and torch.equal(a.inv, b.inv), step
+        np.testing.assert_allclose(to_np(ea), to_np(eb), rtol=1e-12,
+                                   atol=1e-12 * float(np.abs(to_np(eb)).max()))
+        say(f"  step {step}: accepted {int(to_np(ca).sum())} of {nw * 2 * n}")
+    t.free()
