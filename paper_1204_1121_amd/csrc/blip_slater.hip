@@ -168,41 +168,93 @@ __device__ __forceinline__ void sm_build_s(const double* __restrict__ Pp, int n,
     }
 }
 
+// Entry (r, c) of S after the Gauss-Jordan step on pivot p, from s = S[r][c],
+// srp = S[r][p], spc = S[p][c] and rd = 1/S[p][p]: column p becomes
+// -S[r][p]/d, row p becomes S[p][c]/d (1/d on the diagonal), the rest
+// S[r][c] - S[r][p] S[p][c]/d.
+__device__ __forceinline__ double gj_entry(double s, double srp, double spc, double rd,
+                                           bool rowp, bool colp)
+{
+    const double coef = colp ? rd : spc * rd;
+    const double nv = fma(-srp, coef, colp ? 0.0 : s);
+    return rowp ? coef : nv;
+}
+
 // S^{-1} by Gauss-Jordan without pivoting, in registers (the layout of
-// sm_build_s).  Each step publishes pivot row p and column p through
-// double-buffered LDS vectors (one barrier); every thread then reads what it
-// needs in one round trip and updates its 4 entries.  piv[p] receives the
-// pivots, the sequential ratios.  Ends with S^{-1} in Sinv (after a barrier).
+// sm_build_s), two pivots per round.  A round publishes rows p, p+1 and
+// columns p, p+1 through double-buffered LDS vectors (one barrier).  Every
+// thread then forms, from those, row p+1 and column p+1 as step p leaves them
+// and the pivot of step p+1, with exactly the operations the threads that
+// own those entries apply, and takes its 4 entries through both steps: the
+// result is bit for bit that of one pivot per barrier, with half the
+// barriers.  piv[p] receives the pivots, the sequential ratios.  Ends with
+// S^{-1} in Sinv (after a barrier).
 __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
-                                             double (*bc)[2][kSmChunk], double* piv,
+                                             double (*bc)[4][kSmChunk], double* piv,
                                              double (*Sinv)[kSmPad])
 {
     const int gc = tid % kSmChunk;
     const int gr0 = tid / kSmChunk;
-    for (int p = 0; p < kp; ++p) {
-        const int b = p & 1;
-        const int jp = p >> 3;
-        if (gr0 == (p & 7)) bc[b][0][gc] = jp == 0 ? sv[0] : jp == 1 ? sv[1] : jp == 2 ? sv[2] : sv[3];
+    auto mine = [&](int j) { return j == 0 ? sv[0] : j == 1 ? sv[1] : j == 2 ? sv[2] : sv[3]; };
+    int p = 0, round = 0;
+    for (; p + 1 < kp; p += 2, ++round) {
+        const int b = round & 1;
+        if (gr0 == (p & 7)) bc[b][0][gc] = mine(p >> 3);
+        if (gr0 == ((p + 1) & 7)) bc[b][1][gc] = mine((p + 1) >> 3);
         if (gc == p) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bc[b][1][gr0 + 8 * j] = sv[j];
+            for (int j = 0; j < 4; ++j) bc[b][2][gr0 + 8 * j] = sv[j];
+        }
+        if (gc == p + 1) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bc[b][3][gr0 + 8 * j] = sv[j];
         }
         __syncthreads();
         const double d = bc[b][0][p];
-        const double rowv = bc[b][0][gc];
-        double crp[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) crp[j] = bc[b][1][gr0 + 8 * j];
         const double rd = 1.0 / d;
-        // column p becomes -S[r][p]/d, row p becomes S[p][c]/d (1/d on the
-        // diagonal), the rest S[r][c] - S[r][p] S[p][c]/d
-        const bool pcol = (gc == p);
-        const double coef = pcol ? rd : rowv * rd;
+        const double s0c = bc[b][0][gc], s1c = bc[b][1][gc];
+        const double s0q = bc[b][0][p + 1], s1p = bc[b][1][p], s1q = bc[b][1][p + 1];
+        double c0[4], c1[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const double nv = fma(-crp[j], coef, pcol ? 0.0 : sv[j]);
-            sv[j] = (gr0 + 8 * j == p) ? coef : nv;
+            c0[j] = bc[b][2][gr0 + 8 * j];
+            c1[j] = bc[b][3][gr0 + 8 * j];
         }
+        // step p: this thread's entries, row p+1 at column gc, column p+1 at
+        // its rows, and the next pivot
+        const bool colp = gc == p;
+        const double u = gj_entry(s1c, s1p, s0c, rd, false, colp);
+        const double d2 = gj_entry(s1q, s1p, s0q, rd, false, false);
+        const double rd2 = 1.0 / d2;
+        const bool colq = gc == p + 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = gr0 + 8 * j;
+            const double e = gj_entry(sv[j], c0[j], s0c, rd, r == p, colp);
+            const double w = gj_entry(c1[j], c0[j], s0q, rd, r == p, false);
+            // step p + 1
+            sv[j] = gj_entry(e, w, u, rd2, r == p + 1, colq);
+        }
+        if (tid == 0) {
+            piv[p] = d;
+            piv[p + 1] = d2;
+        }
+    }
+    if (p < kp) {   // an odd last pivot: one step
+        const int b = round & 1;
+        if (gr0 == (p & 7)) bc[b][0][gc] = mine(p >> 3);
+        if (gc == p) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bc[b][2][gr0 + 8 * j] = sv[j];
+        }
+        __syncthreads();
+        const double d = bc[b][0][p];
+        const double rd = 1.0 / d;
+        const double s0c = bc[b][0][gc];
+        const bool colp = gc == p;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            sv[j] = gj_entry(sv[j], bc[b][2][gr0 + 8 * j], s0c, rd, gr0 + 8 * j == p, colp);
         if (tid == 0) piv[p] = d;
     }
 #pragma unroll
@@ -215,7 +267,7 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
 // main launch that follows does not eliminate S in every workgroup.
 __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 {
-    __shared__ double bc[2][2][kSmChunk];
+    __shared__ double bc[2][4][kSmChunk];
     __shared__ double Sinv[kSmChunk][kSmPad];
     __shared__ double piv[kSmChunk];
     __shared__ int lcolp[kSmChunk];
@@ -268,7 +320,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
     constexpr int ROWS = 16 * RB;               // rows of B: RB matrix-core row blocks
     constexpr int VPT = ROWS / 8;               // entries of V - E (and Y) per thread
-    __shared__ double bc[2][2][kSmChunk];       // pivot row / column, double-buffered
+    __shared__ double bc[2][4][kSmChunk];       // pivot rows / columns, double-buffered
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
     __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
     __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
