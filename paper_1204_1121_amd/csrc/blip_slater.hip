@@ -75,6 +75,7 @@ struct SmArgs {
     // sizes and electron lists come from device memory; the offsets above
     // are per matrix.
     int chunk;               // this launch applies chunk-1 and prepares chunk
+    int nmat;                // matrices in the batch
     int max_k;               // moves per matrix are clamped to [0, max_k]
     const int* acc_cols;     // [nmat][acc_ld] electrons in move order
     int64_t acc_ld;
@@ -84,6 +85,7 @@ struct SmArgs {
     int64_t ws_mstride;      // doubles between matrices in the workspace
     int64_t ratio_ld;        // ratios of matrix q start at ratio + q * ratio_ld
     const double* sinv;      // [nmat] S^{-1} of the applied chunk, from sm_sinv_kernel
+    int* act;                // [1 + nmat] matrices with moves in the launch, from it
     int vec_b;               // 1: rows of B (every matrix) start 16-byte aligned
     int vec_u;               // 1: rows of u (every matrix) start 16-byte aligned
 };
@@ -130,6 +132,41 @@ __device__ __forceinline__ void sm_batched_counts(const SmArgs& a, int q, int& k
     const int lo = (a.chunk - 1) * kSmChunk, hi = a.chunk * kSmChunk;
     kp = a.chunk > 0 ? min(max(cnt - lo, 0), kSmChunk) : 0;
     kn = min(max(cnt - hi, 0), kSmChunk);
+}
+
+// Whether matrix qq has moves in a batched launch whose applied chunk starts
+// at move lo: its clamped count exceeds lo.
+__device__ __forceinline__ bool sm_batched_active(const SmArgs& a, int qq, int lo)
+{
+    int cnt = a.acc_count[qq];
+    cnt = cnt < 0 ? 0 : (cnt > a.max_k ? a.max_k : cnt);
+    return cnt > lo;
+}
+
+// The matrices with moves in a batched launch whose applied chunk starts at
+// move lo, listed in matrix order by one workgroup: act[1 + i] is the i-th,
+// act[0] their number.
+__device__ void sm_list_active(const SmArgs& a, int lo, int tid, int* act, int* s_wc)
+{
+    const int lane = tid & (kWave - 1), w = tid / kWave;
+    int run = 0;
+    for (int base = 0; base < a.nmat; base += kSmThreads) {
+        const int qq = base + tid;
+        const bool on = qq < a.nmat && sm_batched_active(a, qq, lo);
+        const unsigned long long m = __ballot(on);
+        if (lane == 0) s_wc[w] = __popcll(m);
+        __syncthreads();
+        int pre = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < kSmWaves; ++k) {
+            pre += k < w ? s_wc[k] : 0;
+            tot += s_wc[k];
+        }
+        if (on) act[1 + run + pre + __popcll(m & ((1ull << lane) - 1ull))] = qq;
+        run += tot;
+        __syncthreads();   // s_wc is rewritten in the next round
+    }
+    if (tid == 0) act[0] = run;
 }
 
 // Electron m of chunk ch of matrix q (clamped into [0, n): bad lists give
@@ -264,7 +301,8 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
 
 // Batched form only: S^{-1} of chunk (chunk-1) of matrix blockIdx.x, and its
 // pivots written to the matrix's ratios.  One workgroup per matrix, so the
-// main launch that follows does not eliminate S in every workgroup.
+// main launch that follows does not eliminate S in every workgroup; one more
+// lists the matrices that have moves in that launch.
 __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 {
     __shared__ double bc[2][4][kSmChunk];
@@ -273,6 +311,11 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
     __shared__ int lcolp[kSmChunk];
     const int q = blockIdx.x;
     const int tid = threadIdx.x;
+    if (q == a.nmat) {   // the extra workgroup: the chunk launch's matrices
+        __shared__ int s_wc[kSmWaves];
+        sm_list_active(a, (a.chunk - 1) * kSmChunk, tid, a.act, s_wc);
+        return;
+    }
     int kp, kn;
     sm_batched_counts(a, q, kp, kn);
     if (kp == 0) return;   // uniform over the workgroup
@@ -342,13 +385,34 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // The batched launch is one workgroup per (matrix, row block), its index
     // mapped so that the row blocks of a matrix run on one XCD and share that
     // XCD's L2 copy of the matrix's R and U (round-robin dispatch would give
-    // every XCD a copy).
+    // every XCD a copy); each walks all column tiles of its rows.  Once few
+    // matrices still have moves (the ragged end of a batch, at most one in
+    // nct of them), their (row block, column tile) pairs get a workgroup each
+    // instead, so that the launch takes a third of the walk's time; every
+    // output still takes the same operations in the same order.
     int q = 0, rblk = (int)blockIdx.x;
+    int y0 = BATCHED ? 0 : (int)blockIdx.y, y1 = BATCHED ? nct : y0 + 1;
     if constexpr (BATCHED) {
         const int nrb = (n + ROWS - 1) / ROWS;
-        const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-        q = t / nrb;
-        rblk = t - q * nrb;
+        // the first launch prepares every matrix with moves: no list
+        int nact = (a.chunk > 0 && nct > 1) ? a.act[0] : a.nmat;
+        nact = nact < 0 ? 0 : (nact > a.nmat ? a.nmat : nact);
+        if (nct > 1 && nact * nct <= a.nmat) {
+            const int used = nact * nrb * nct;   // <= nmat * nrb, the grid
+            if ((int)blockIdx.x >= used) return;   // uniform per workgroup
+            const int t = xcd_tile((int)blockIdx.x, used);
+            const int i = t / (nrb * nct);
+            const int rem = t - i * (nrb * nct);
+            rblk = rem / nct;
+            y0 = rem - rblk * nct;
+            y1 = y0 + 1;
+            q = a.act[1 + i];
+            q = q < 0 ? 0 : (q >= a.nmat ? a.nmat - 1 : q);
+        } else {
+            const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+            q = t / nrb;
+            rblk = t - q * nrb;
+        }
     }
     if constexpr (BATCHED) {
         sm_batched_counts(a, q, kp, kn);
@@ -526,11 +590,10 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         }
     };
 
-    // The batched form walks every column tile of its rows (one prologue per
-    // matrix row block); the single form takes the column tile blockIdx.y.
-    // V partials are kept per column tile either way, in the same order.
-    const int y0 = BATCHED ? 0 : (int)blockIdx.y;
-    const int y1 = BATCHED ? nct : y0 + 1;
+    // The batched form walks the column tiles [y0, y1) of its rows (all of
+    // them, or one at the ragged end of a batch); the single form takes the
+    // column tile blockIdx.y.  V partials are kept per column tile either
+    // way, in the same order.
     for (int y = y0; y < y1; ++y) {
         const int c0 = y * a.tl;
         const int cend = min(n, c0 + a.tl);
@@ -757,7 +820,11 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
 BLIP_API size_t blip_sm_batched_workspace_size(int nmat, int64_t n)
 {
     if (nmat < 0 || n <= 0 || n > kSmMaxN) return 0;
-    return (size_t)nmat * (size_t)sm_ws_doubles(n) * sizeof(double);
+    // per matrix: V partials, moved rows and S^{-1}; then the list of the
+    // matrices with moves in a launch
+    const size_t bytes = (size_t)nmat * (size_t)sm_ws_doubles(n) * sizeof(double) +
+                         ((size_t)nmat + 1) * sizeof(int);
+    return (bytes + 255) / 256 * 256;
 }
 
 BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t inv_mstride,
@@ -820,6 +887,8 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     a.ws_mstride = ws_m;
     a.ratio_ld = ratio_ld;
     a.sinv = S;
+    a.nmat = nmat;
+    a.act = reinterpret_cast<int*>(static_cast<double*>(workspace) + (size_t)nmat * ws_m);
     // launch c applies chunk c-1 (S^{-1} from the launch of sm_sinv_kernel
     // just before it) and prepares chunk c
     for (int c = 0; c <= nchunks; ++c) {
@@ -827,7 +896,7 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         if (c > 0) {
             a.Pp = V[(c - 1) & 1];
             a.Rp = R[(c - 1) & 1];
-            hipLaunchKernelGGL(sm_sinv_kernel, dim3((unsigned)nmat), dim3(kSmThreads), 0, s, a);
+            hipLaunchKernelGGL(sm_sinv_kernel, dim3((unsigned)nmat + 1), dim3(kSmThreads), 0, s, a);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return fail_hip(e, "sm_sinv_kernel launch");
         }

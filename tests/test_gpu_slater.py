@@ -293,6 +293,41 @@ def test_batched_extreme_orders(blip, n):
         np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
 
 
+@pytest.mark.parametrize("nmat", [12, 60])
+def test_batched_ragged_end_bitwise(blip, nmat):
+    """Ragged move counts at an order with three column tiles: the later
+    launches have few matrices with moves, and there each (row block, column
+    tile) gets a workgroup of its own.  Every matrix still equals the
+    single-matrix update bit for bit (one and two row blocks per workgroup)."""
+    n = 600
+    rng = np.random.default_rng(900 + nmat)
+    D, inv0, _, U0 = case(901, n, 1)
+    invs = np.stack([inv0 * (1.0 + 0.01 * q) for q in range(nmat)])
+    counts = rng.integers(0, 120, nmat)
+    counts[:4] = [0, 33, 600, 451]          # a long tail: 2, then 1 matrix active
+    max_k = int(counts.max())
+    acc = np.zeros((nmat, max_k), dtype=np.int32)
+    lists = []
+    for q in range(nmat):
+        c = rng.permutation(n)[: counts[q]].astype(np.int64)
+        acc[q, : len(c)] = c
+        lists.append(c)
+    say(f"batched SM, ragged end: {nmat} matrices of n = {n}, counts up to {max_k}")
+    inv_b = torch.from_numpy(invs).cuda()
+    U = torch.from_numpy(U0).cuda()
+    r_b = blip.sm_update_batched(inv_b, U.unsqueeze(0).expand(nmat, n, n).contiguous(),
+                                 torch.from_numpy(acc).cuda(),
+                                 torch.from_numpy(counts.astype(np.int32)).cuda(), max_k)
+    torch.cuda.synchronize()
+    got_inv, got_r = to_np(inv_b), to_np(r_b)
+    for q in (0, 1, 2, 3, nmat - 1):
+        inv1 = torch.from_numpy(invs[q]).cuda()
+        r1 = blip.sm_update(inv1, U, lists[q])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got_inv[q], to_np(inv1), err_msg=f"matrix {q}")
+        np.testing.assert_array_equal(got_r[q, : counts[q]], to_np(r1), err_msg=f"ratios {q}")
+
+
 def test_batched_padded_strides_and_untouched(blip):
     """Matrices with padded rows inside a wider buffer, u with extra rows:
     columns past n and matrices with no moves are left as they were."""
