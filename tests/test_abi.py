@@ -219,3 +219,14 @@ def test_qs_helpers_argument_errors(blip):
                                     None) == -1
     assert L.blip_eval_ratio_values(None, dev, 4, dev, 8, None, dev, None, None, dev, dev,
                                     None) == -1
+    # and so does its batched form, which also needs the values, 4-byte
+    # aligned, before it looks at the table
+    rvb = L.blip_eval_ratio_values_batched
+    assert rvb(None, dev, dev, 1, 4, dev, 8, None, dev, dev, dev, dev, None, dev, 1 << 20,
+               None) == -1
+    assert rvb(None, dev, dev, 1, 4, dev, 8, None, dev, None, None, None, None, dev, 1 << 20,
+               None) == -1
+    assert rvb(None, dev, dev, 1, 4, dev, 8, None, dev, None, None, ctypes.c_void_p(0x10002),
+               None, dev, 1 << 20, None) == -5
+    assert rvb(None, dev, dev, 1, 4, dev, 8, None, dev, None, None, dev, None, dev, 1 << 20,
+               None) == -6
