@@ -385,17 +385,19 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // The batched launch is one workgroup per (matrix, row block), its index
     // mapped so that the row blocks of a matrix run on one XCD and share that
     // XCD's L2 copy of the matrix's R and U (round-robin dispatch would give
-    // every XCD a copy); each walks all column tiles of its rows.  Once few
-    // matrices still have moves (the ragged end of a batch, at most one in
-    // nct of them), their (row block, column tile) pairs get a workgroup each
-    // instead, so that the launch takes a third of the walk's time; every
-    // output still takes the same operations in the same order.
+    // every XCD a copy); each walks all column tiles of its rows.  Once some
+    // matrices have no moves left, only the listed ones (sm_sinv_kernel) get
+    // workgroups, spread evenly over the XCDs; once few still have moves (the
+    // ragged end of a batch, at most one in nct of them), their (row block,
+    // column tile) pairs get a workgroup each instead of a walk, so that the
+    // launch takes a third of the walk's time.  Every output still takes the
+    // same operations in the same order.
     int q = 0, rblk = (int)blockIdx.x;
     int y0 = BATCHED ? 0 : (int)blockIdx.y, y1 = BATCHED ? nct : y0 + 1;
     if constexpr (BATCHED) {
         const int nrb = (n + ROWS - 1) / ROWS;
         // the first launch prepares every matrix with moves: no list
-        int nact = (a.chunk > 0 && nct > 1) ? a.act[0] : a.nmat;
+        int nact = a.chunk > 0 ? a.act[0] : a.nmat;
         nact = nact < 0 ? 0 : (nact > a.nmat ? a.nmat : nact);
         if (nct > 1 && nact * nct <= a.nmat) {
             const int used = nact * nrb * nct;   // <= nmat * nrb, the grid
@@ -406,6 +408,16 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
             rblk = rem / nct;
             y0 = rem - rblk * nct;
             y1 = y0 + 1;
+            q = a.act[1 + i];
+            q = q < 0 ? 0 : (q >= a.nmat ? a.nmat - 1 : q);
+        } else if (nact < a.nmat) {
+            // some matrices are done: walk over the listed ones only, so
+            // that they spread evenly over the XCDs
+            const int used = nact * nrb;
+            if ((int)blockIdx.x >= used) return;   // uniform per workgroup
+            const int t = xcd_tile((int)blockIdx.x, used);
+            const int i = t / nrb;
+            rblk = t - i * nrb;
             q = a.act[1 + i];
             q = q < 0 ? 0 : (q >= a.nmat ? a.nmat - 1 : q);
         } else {
