@@ -218,44 +218,36 @@ __device__ __forceinline__ double gj_entry(double s, double srp, double spc, dou
 }
 
 // S^{-1} by Gauss-Jordan without pivoting, in registers (the layout of
-// sm_build_s), two pivots per round.  A round publishes rows p, p+1 and
-// columns p, p+1 through double-buffered LDS vectors (one barrier).  Every
-// thread then forms, from those, row p+1 and column p+1 as step p leaves them
-// and the pivot of step p+1, with exactly the operations the threads that
-// own those entries apply, and takes its 4 entries through both steps: the
-// result is bit for bit that of one pivot per barrier, with half the
-// barriers.  piv[p] receives the pivots, the sequential ratios.  Ends with
-// S^{-1} in Sinv (after a barrier).
+// sm_build_s), two pivots per round.  A round publishes the whole of S to one
+// of two LDS copies (every thread stores its 4 entries: no branches) and
+// takes one barrier.  Every thread then reads rows p, p+1 at its column and
+// columns p, p+1 at its rows, forms row p+1 and column p+1 as step p leaves
+// them and the pivot of step p+1, with exactly the operations the threads
+// that own those entries apply, and takes its 4 entries through both steps:
+// the result is bit for bit that of one pivot per barrier.  piv[p] receives
+// the pivots, the sequential ratios.  Ends with S^{-1} in Sinv (after a
+// barrier).
 __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
-                                             double (*bc)[4][kSmChunk], double* piv,
+                                             double (*Sx)[kSmChunk][kSmChunk], double* piv,
                                              double (*Sinv)[kSmPad])
 {
     const int gc = tid % kSmChunk;
     const int gr0 = tid / kSmChunk;
-    auto mine = [&](int j) { return j == 0 ? sv[0] : j == 1 ? sv[1] : j == 2 ? sv[2] : sv[3]; };
     int p = 0, round = 0;
     for (; p + 1 < kp; p += 2, ++round) {
-        const int b = round & 1;
-        if (gr0 == (p & 7)) bc[b][0][gc] = mine(p >> 3);
-        if (gr0 == ((p + 1) & 7)) bc[b][1][gc] = mine((p + 1) >> 3);
-        if (gc == p) {
+        double (*S)[kSmChunk] = Sx[round & 1];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bc[b][2][gr0 + 8 * j] = sv[j];
-        }
-        if (gc == p + 1) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bc[b][3][gr0 + 8 * j] = sv[j];
-        }
+        for (int j = 0; j < 4; ++j) S[gr0 + 8 * j][gc] = sv[j];
         __syncthreads();
-        const double d = bc[b][0][p];
+        const double d = S[p][p];
         const double rd = 1.0 / d;
-        const double s0c = bc[b][0][gc], s1c = bc[b][1][gc];
-        const double s0q = bc[b][0][p + 1], s1p = bc[b][1][p], s1q = bc[b][1][p + 1];
+        const double s0c = S[p][gc], s1c = S[p + 1][gc];
+        const double s0q = S[p][p + 1], s1p = S[p + 1][p], s1q = S[p + 1][p + 1];
         double c0[4], c1[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            c0[j] = bc[b][2][gr0 + 8 * j];
-            c1[j] = bc[b][3][gr0 + 8 * j];
+            c0[j] = S[gr0 + 8 * j][p];
+            c1[j] = S[gr0 + 8 * j][p + 1];
         }
         // step p: this thread's entries, row p+1 at column gc, column p+1 at
         // its rows, and the next pivot
@@ -278,20 +270,17 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
         }
     }
     if (p < kp) {   // an odd last pivot: one step
-        const int b = round & 1;
-        if (gr0 == (p & 7)) bc[b][0][gc] = mine(p >> 3);
-        if (gc == p) {
+        double (*S)[kSmChunk] = Sx[round & 1];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bc[b][2][gr0 + 8 * j] = sv[j];
-        }
+        for (int j = 0; j < 4; ++j) S[gr0 + 8 * j][gc] = sv[j];
         __syncthreads();
-        const double d = bc[b][0][p];
+        const double d = S[p][p];
         const double rd = 1.0 / d;
-        const double s0c = bc[b][0][gc];
+        const double s0c = S[p][gc];
         const bool colp = gc == p;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            sv[j] = gj_entry(sv[j], bc[b][2][gr0 + 8 * j], s0c, rd, gr0 + 8 * j == p, colp);
+            sv[j] = gj_entry(sv[j], S[gr0 + 8 * j][p], s0c, rd, gr0 + 8 * j == p, colp);
         if (tid == 0) piv[p] = d;
     }
 #pragma unroll
@@ -305,7 +294,7 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
 // lists the matrices that have moves in that launch.
 __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 {
-    __shared__ double bc[2][4][kSmChunk];
+    __shared__ double Sx[2][kSmChunk][kSmChunk];
     __shared__ double Sinv[kSmChunk][kSmPad];
     __shared__ double piv[kSmChunk];
     __shared__ int lcolp[kSmChunk];
@@ -324,7 +313,7 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
     const double* Pp = a.Pp + q * a.ws_mstride;
     double sv[4];
     sm_build_s(Pp, a.n, a.nct, kp, lcolp, tid, sv);
-    sm_eliminate(kp, tid, sv, bc, piv, Sinv);
+    sm_eliminate(kp, tid, sv, Sx, piv, Sinv);
     double* out = const_cast<double*>(a.sinv) + q * a.ws_mstride;
     for (int e = tid; e < kSmChunk * kSmPad; e += kSmThreads) out[e] = (&Sinv[0][0])[e];
     if (a.ratio != nullptr && tid < kp)
@@ -363,7 +352,6 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
     constexpr int ROWS = 16 * RB;               // rows of B: RB matrix-core row blocks
     constexpr int VPT = ROWS / 8;               // entries of V - E (and Y) per thread
-    __shared__ double bc[2][4][kSmChunk];       // pivot rows / columns, double-buffered
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
     __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
     __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
@@ -491,9 +479,10 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
             const double* src = a.sinv + q * a.ws_mstride;
             for (int e = tid; e < kSmChunk * kSmPad; e += kSmThreads) (&Sinv[0][0])[e] = src[e];
         } else {
+            __shared__ double Sx[2][kSmChunk][kSmChunk];   // S, double-buffered
             double sv[4];
             sm_build_s(Pp, n, nct, kp, lcolp, tid, sv);
-            sm_eliminate(kp, tid, sv, bc, piv, Sinv);
+            sm_eliminate(kp, tid, sv, Sx, piv, Sinv);
         }
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
