@@ -43,6 +43,7 @@ from __future__ import annotations
 import torch
 
 from . import blip as _b
+from .tuning import TuneCache
 
 # From this many trial moves per step on, the ratio pass runs as one sorted
 # persistent launch over all walkers; below it the sort's five small launches
@@ -81,6 +82,9 @@ class Walkers:
         if self.sorted:
             self.off = torch.tensor([0, npos], dtype=torch.int64, device=dev)
             self.rws = table.workspace(npos, dev)
+            # the ratio pass's launch shape measured for this table and step
+            # size, if the package's tuning cache holds one (else the default)
+            TuneCache().apply(table, npos, batched=True, ratio=True)
         if inv_t is None:
             self.t.eval(self.pos.view(npos, 3), grad=False, out=(self.val, None, None),
                         stream=stream)
