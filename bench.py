@@ -605,6 +605,8 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
     log(f"vmc: {t_step * 1e6:.0f} us per quasi-simultaneous step of {W} walkers x {2 * n} "
         f"electrons ({W / t_step:.0f} walker-steps/s, acceptance {acc:.2f})")
 
+    if args.no_vmc_stats:
+        return res
     # -- statistics: quasi-simultaneous against configuration-by-configuration
     A = np.array([[6.0, 0.3, 0.0], [0.2, 5.0, 0.4], [0.0, -0.3, 5.5]])
     ng, Ls, Ws = (12, 11, 10), 8, 64
@@ -875,6 +877,8 @@ def main():
                     help="skip the values-only complex section at the paper's system sizes")
     ap.add_argument("--no-vmc", action="store_true",
                     help="skip the Monte Carlo step throughput and statistics section")
+    ap.add_argument("--no-vmc-stats", action="store_true",
+                    help="keep the Monte Carlo step throughput, skip its statistics chains")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving rate point")
     ap.add_argument("--copy-probe", action="store_true",
