@@ -230,13 +230,29 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
                            blip_tune_result* results, int max_results, int* n_results,
                            blip_tune_result* best);
 
-/* blip_set_shape / blip_get_shape -- set or read the launch shape used for
- * npos's size bucket, the power-of-two range [2^k, 2^(k+1)) holding npos
- * (batched != 0: the batched path), e.g. to restore a cached autotuning
- * result.  A size whose bucket has no shape of its own uses one set for an
- * adjacent bucket (the larger if both are), else the built-in default. */
-BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec);
-BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec);
+/* Launch-shape modes of blip_set_shape / blip_get_shape: the single-block
+ * launch and the sorted persistent batch, each plain (orbitals stored) or
+ * with the acceptance-ratio epilogue (blip_eval_ratio* calls).  A ratio
+ * mode with no shape of its own runs its plain mode's shape, capped as the
+ * epilogue needs (P <= 16 positions, at most 16 orbital chunks). */
+typedef enum {
+    BLIP_SHAPE_BLOCK = 0,          /* blip_eval, blip_eval_ex (tiled)          */
+    BLIP_SHAPE_BATCHED = 1,        /* blip_eval_batched, plans                 */
+    BLIP_SHAPE_BLOCK_RATIO = 2,    /* blip_eval_ratio, blip_eval_ratio_values  */
+    BLIP_SHAPE_BATCHED_RATIO = 3   /* blip_eval_ratio_batched,
+                                      blip_eval_ratio_values_batched           */
+} blip_shape_mode;
+
+/* blip_set_shape / blip_get_shape -- set or read the launch shape that mode
+ * (a blip_shape_mode) uses for npos's size bucket, the power-of-two range
+ * [2^k, 2^(k+1)) holding npos, e.g. to restore a cached autotuning result.
+ * A size whose bucket has no shape of its own uses one set for an adjacent
+ * bucket of the same mode (the larger if both are), else the built-in
+ * default.  blip_get_shape reports what a launch of npos positions in that
+ * mode would run.  Errors: BLIP_E_STATE (handle), BLIP_E_ARG (mode, npos < 1,
+ * tile_pos outside 1..64, vec not valid for the table's storage). */
+BLIP_API int blip_set_shape(blip_table t, int mode, int64_t npos, int tile_pos, int vec);
+BLIP_API int blip_get_shape(blip_table t, int mode, int64_t npos, int* tile_pos, int* vec);
 
 /*
  * blip_eval_ratio -- quasi-simultaneous acceptance ratios of the Slater part
@@ -305,12 +321,13 @@ BLIP_API int blip_eval_ratio_batched(blip_table t, const double* pos, const int6
  * walkers (both spins) evaluated as one set of positions (Eq. (11.12.23.1)
  * makes every trial move independent), in spatial order so that moves of
  * different walkers near the same grid sites share the rows they read.
- * val [capacity][L] float is required; grad_ratio, lap_ratio and lap
- * [capacity][L] float go together or not at all, as in
- * blip_eval_ratio_values.  Rows j < offsets[nw] are written at index j (the
- * caller's order).  The values and Laplacian rows equal blip_eval's bit for
- * bit; the ratios equal blip_eval_ratio_values' when both run with the same
- * orbitals per lane (blip_set_shape), as they sum the same per-lane products
+ * val [capacity][L] float is required.  grad_ratio [capacity][3] double,
+ * lap_ratio [capacity] double and lap [capacity][L] float go together or not
+ * at all, as in blip_eval_ratio_values.  Rows j < offsets[nw] are written at
+ * index j (the caller's order).  The values and Laplacian rows equal
+ * blip_eval's bit for bit; the ratios equal blip_eval_ratio_values' when both
+ * run with the same orbitals per lane (blip_set_shape with
+ * BLIP_SHAPE_BLOCK_RATIO and BLIP_SHAPE_BATCHED_RATIO), as they sum the same per-lane products
  * in the same order.  Same workspace and errors as blip_eval_ratio_batched,
  * plus BLIP_E_ARG without val and BLIP_E_ALIGN for val or lap not 4-byte
  * aligned.  Asynchronous on the stream; the sort and the evaluation make five

@@ -397,13 +397,22 @@ class Table:
         conv = lambda r: {"tile_pos": r.tile_pos, "vec": r.vec, "us": r.us}
         return conv(best), [conv(res[i]) for i in range(n.value)]
 
-    def set_shape(self, npos: int, tile_pos: int, vec: int, batched: bool = False) -> None:
-        check(lib().blip_set_shape(self.handle, int(batched), int(npos), int(tile_pos), int(vec)))
+    @staticmethod
+    def _shape_mode(batched: bool, ratio: bool) -> int:
+        # blip_shape_mode: block 0, batched 1, block ratio 2, batched ratio 3
+        return (1 if batched else 0) + (2 if ratio else 0)
 
-    def get_shape(self, npos: int, batched: bool = False):
+    def set_shape(self, npos: int, tile_pos: int, vec: int, batched: bool = False,
+                  ratio: bool = False) -> None:
+        """Launch shape for npos's size bucket: the single-block or batched
+        path, plain or with the acceptance-ratio epilogue (ratio=True)."""
+        check(lib().blip_set_shape(self.handle, self._shape_mode(batched, ratio), int(npos),
+                                   int(tile_pos), int(vec)))
+
+    def get_shape(self, npos: int, batched: bool = False, ratio: bool = False):
         P, o = ctypes.c_int(), ctypes.c_int()
-        check(lib().blip_get_shape(self.handle, int(batched), int(npos), ctypes.byref(P),
-                                   ctypes.byref(o)))
+        check(lib().blip_get_shape(self.handle, self._shape_mode(batched, ratio), int(npos),
+                                   ctypes.byref(P), ctypes.byref(o)))
         return P.value, o.value
 
     def free(self) -> None:

@@ -300,7 +300,7 @@ static int ratio_batched(blip_table t, const double* pos, const int64_t* offsets
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
         return fail(BLIP_E_ALIGN, "workspace must be 256-byte aligned");
     int P = 0, OE = 0;
-    rc = ratio_shape(t, MODE_BATCHED, capacity, P, OE);
+    rc = ratio_shape(t, MODE_BATCHED_RATIO, capacity, P, OE);
     if (rc != BLIP_OK) return rc;
     const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, gratio, lratio};
     return enqueue_batched(t, pos, offsets, nw, capacity, val, nullptr, lap, workspace, P, OE, s,
@@ -511,21 +511,28 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
     return BLIP_OK;
 }
 
-BLIP_API int blip_set_shape(blip_table t, int batched, int64_t npos, int tile_pos, int vec)
+BLIP_API int blip_set_shape(blip_table t, int mode, int64_t npos, int tile_pos, int vec)
 {
     if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (mode < 0 || mode >= MODE_COUNT) return fail(BLIP_E_ARG, "mode must be 0..%d", MODE_COUNT - 1);
     if (tile_pos < 1 || tile_pos > kMaxTile) return fail(BLIP_E_ARG, "tile_pos must be 1..%d", kMaxTile);
     if (!valid_oe(t, vec)) return fail(BLIP_E_ARG, "vec=%d not supported for this table", vec);
     if (npos < 1) return fail(BLIP_E_ARG, "npos must be >= 1");
-    set_tuned(t, batched ? MODE_BATCHED : MODE_BLOCK, npos, tile_pos, vec);
+    set_tuned(t, mode, npos, tile_pos, vec);
     return BLIP_OK;
 }
 
-BLIP_API int blip_get_shape(blip_table t, int batched, int64_t npos, int* tile_pos, int* vec)
+BLIP_API int blip_get_shape(blip_table t, int mode, int64_t npos, int* tile_pos, int* vec)
 {
     if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (mode < 0 || mode >= MODE_COUNT) return fail(BLIP_E_ARG, "mode must be 0..%d", MODE_COUNT - 1);
     int P, OE;
-    choose_shape(t, batched ? MODE_BATCHED : MODE_BLOCK, npos, P, OE);
+    int rc = BLIP_OK;
+    if (mode == MODE_BLOCK_RATIO || mode == MODE_BATCHED_RATIO)
+        rc = ratio_shape(t, mode, npos, P, OE);
+    else
+        choose_shape(t, mode, npos, P, OE);
+    if (rc != BLIP_OK) return rc;
     if (tile_pos) *tile_pos = P;
     if (vec) *vec = OE;
     return BLIP_OK;

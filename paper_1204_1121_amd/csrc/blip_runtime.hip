@@ -126,31 +126,38 @@ static void bucket(int64_t npos, int64_t& lo, int64_t& hi)
     hi = lo * 2 - 1;
 }
 
-// The tuned shape of npos's bucket; failing that, one tuned for an adjacent
-// bucket (a batch just under a power of two keeps the shape tuned just above
-// it); failing that, the default.
+// The shape kept for npos's bucket in one mode, else one kept for an
+// adjacent bucket (a batch just under a power of two keeps the shape tuned
+// just above it; the larger if both are); false if the mode has neither.
+static bool lookup_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
+{
+    std::lock_guard<std::mutex> lk(t->tune_mu);
+    const TuneEntry* near = nullptr;
+    for (const TuneEntry& e : t->tune[mode]) {
+        if (npos >= e.lo && npos <= e.hi) {
+            P = e.P;
+            OE = e.OE;
+            return true;
+        }
+        const bool adjacent = (npos < e.lo && npos >= e.lo / 2) ||
+                              (npos > e.hi && npos <= 2 * e.hi + 1);
+        if (adjacent && (near == nullptr || e.lo > near->lo)) near = &e;
+    }
+    if (near == nullptr) return false;
+    P = near->P;
+    OE = near->OE;
+    return true;
+}
+
+// The shape a launch of npos positions runs in a mode: its own kept shape; for
+// a ratio mode with none, the plain mode's; failing that, the default.
 void choose_shape(const blip_table_s* t, int mode, int64_t npos, int& P, int& OE)
 {
-    {
-        std::lock_guard<std::mutex> lk(t->tune_mu);
-        const TuneEntry* near = nullptr;
-        for (const TuneEntry& e : t->tune[mode]) {
-            if (npos >= e.lo && npos <= e.hi) {
-                P = e.P;
-                OE = e.OE;
-                return;
-            }
-            const bool adjacent = (npos < e.lo && npos >= e.lo / 2) ||
-                                  (npos > e.hi && npos <= 2 * e.hi + 1);
-            if (adjacent && (near == nullptr || e.lo > near->lo)) near = &e;
-        }
-        if (near != nullptr) {
-            P = near->P;
-            OE = near->OE;
-            return;
-        }
-    }
-    default_shape(t, mode, npos, P, OE);
+    if (lookup_shape(t, mode, npos, P, OE)) return;
+    const int base = (mode == MODE_BLOCK_RATIO) ? MODE_BLOCK
+                   : (mode == MODE_BATCHED_RATIO) ? MODE_BATCHED : mode;
+    if (base != mode && lookup_shape(t, base, npos, P, OE)) return;
+    default_shape(t, base, npos, P, OE);
 }
 
 void set_tuned(blip_table_s* t, int mode, int64_t npos, int P, int OE)
@@ -525,7 +532,7 @@ BLIP_API int blip_eval_ratio(blip_table t, const double* pos, int64_t npos,
                               lap_ratio);
     if (rc != BLIP_OK || npos == 0) return rc;
     int P = 0, OE = 0;
-    rc = ratio_shape(t, MODE_BLOCK, npos, P, OE);
+    rc = ratio_shape(t, MODE_BLOCK_RATIO, npos, P, OE);
     if (rc != BLIP_OK) return rc;
     const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, grad_ratio, lap_ratio};
     return launch_tiled(t, pos, npos, nullptr, nullptr, nullptr, KIND_TILED, P, OE, nullptr,
@@ -545,7 +552,7 @@ BLIP_API int blip_eval_ratio_values(blip_table t, const double* pos, int64_t npo
     if ((reinterpret_cast<uintptr_t>(val) & 3u) != 0 || (reinterpret_cast<uintptr_t>(lap) & 3u) != 0)
         return fail(BLIP_E_ALIGN, "val and lap need 4-byte alignment");
     int P = 0, OE = 0;
-    rc = ratio_shape(t, MODE_BLOCK, npos, P, OE);
+    rc = ratio_shape(t, MODE_BLOCK_RATIO, npos, P, OE);
     if (rc != BLIP_OK) return rc;
     const RatioArgs ra{inv_rows, inv_ld, row_of, ratio, gratio, lratio};
     return launch_tiled(t, pos, npos, val, nullptr, lap, KIND_TILED, P, OE, nullptr, nullptr,

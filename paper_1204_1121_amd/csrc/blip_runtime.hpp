@@ -31,8 +31,11 @@ struct RatioArgs {
     double* lratio;
 };
 
-// Launch-shape tables kept per table: single blocks, and sorted batches.
-enum TuneMode { MODE_BLOCK = 0, MODE_BATCHED = 1 };
+// Launch-shape tables kept per table: single blocks and sorted batches, each
+// with and without the acceptance-ratio epilogue (a ratio mode falls back to
+// its plain mode's shapes when it has none of its own).
+enum TuneMode { MODE_BLOCK = 0, MODE_BATCHED = 1, MODE_BLOCK_RATIO = 2, MODE_BATCHED_RATIO = 3,
+                MODE_COUNT = 4 };
 
 }  // namespace blip
 
@@ -66,7 +69,7 @@ struct blip_table_s {
     int nbins;
     int* d_brick_rank;   // [nb0][nb1][nb2] -> Morton rank
     mutable std::mutex tune_mu;
-    std::vector<blip::TuneEntry> tune[2];   // indexed by blip::TuneMode
+    std::vector<blip::TuneEntry> tune[blip::MODE_COUNT];   // indexed by blip::TuneMode
 };
 
 namespace blip {

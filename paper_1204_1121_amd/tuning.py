@@ -7,9 +7,10 @@ block or batched), outputs (with derivatives, or values only) and the
 power-of-two size bucket, and restores them into a table with
 blip_set_shape, so a run does not need to re-tune.  Shapes measured for the
 acceptance-ratio pass (the ratio epilogue with the values and Laplacian rows)
-are kept under their own path.  A table holds one shape per size bucket, so a
-caller that uses one table for several output modes restores the mode it
-runs.
+are kept under their own path and restored into the table's ratio mode, so
+they never change the shape of a plain launch.  A table holds one shape per
+size bucket and mode, so a caller that uses one table for values only and for
+derivatives restores the output mode it runs.
 """
 from __future__ import annotations
 
@@ -61,7 +62,7 @@ class TuneCache:
         e = self.get(table, npos, batched, values_only, ratio)
         if e is None:
             return False
-        table.set_shape(npos, e["tile_pos"], e["vec"], batched=batched)
+        table.set_shape(npos, e["tile_pos"], e["vec"], batched=batched, ratio=ratio)
         return True
 
     def save(self, path: str | None = None) -> None:

@@ -163,6 +163,27 @@ def test_autotune(blip, small):
         np.testing.assert_array_equal(y[k], ref[k])
 
 
+def test_ratio_shapes_kept_apart(blip, small):
+    """A shape set for the ratio epilogue changes only the ratio launches of
+    its path: the plain batched and block shapes of the same size bucket stay
+    as they were, and a ratio mode with no shape of its own runs its plain
+    mode's shape."""
+    A, n, c, t = small
+    cap = 20000
+    say("launch-shape modes: ratio shapes kept apart from plain shapes")
+    t.set_shape(cap, 16, 2, batched=True)
+    t.set_shape(cap, 2, 1)
+    assert t.get_shape(cap, batched=True, ratio=True) == (16, 2)     # falls back
+    t.set_shape(cap, 4, 4, batched=True, ratio=True)
+    t.set_shape(cap, 8, 4, ratio=True)
+    assert t.get_shape(cap, batched=True) == (16, 2)
+    assert t.get_shape(cap) == (2, 1)
+    assert t.get_shape(cap, batched=True, ratio=True) == (4, 4)
+    assert t.get_shape(cap, ratio=True) == (8, 4)
+    with pytest.raises(RuntimeError):
+        blip.check(blip.lib().blip_set_shape(t.handle, 4, cap, 4, 4))     # no such mode
+
+
 def test_tio2_512_walkers(blip):
     """The batched workload: 512 walkers, blocks of U[1,256] positions on the
     72x72x48 x 768 table; bitwise equal to one blip_eval of the

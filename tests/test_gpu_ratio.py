@@ -226,8 +226,8 @@ def test_ratio_values_batched(blip, o):
     row_of = torch.from_numpy(np.concatenate([allrows, np.zeros(5, np.int64)])).cuda()
     p = torch.from_numpy(np.concatenate([pos, np.zeros((5, 3))])).cuda()
     offs = torch.from_numpy(off).cuda()
-    t.set_shape(total, 8, o)
-    t.set_shape(cap, 8, o, batched=True)
+    t.set_shape(total, 8, o, ratio=True)
+    t.set_shape(cap, 8, o, batched=True, ratio=True)
     say(f"batched ratio values: {nwalk} walkers, {total} moves, L={L}, o={o}")
     out = (torch.full((cap,), 7.0, dtype=torch.float64, device="cuda"),
            torch.full((cap, 3), 7.0, dtype=torch.float64, device="cuda"),

@@ -13,8 +13,8 @@ class FakeTable:
         self.storage, self.norb, self.n = storage, norb, n
         self.calls = []
 
-    def set_shape(self, npos, tile_pos, vec, batched=False):
-        self.calls.append((npos, tile_pos, vec, batched))
+    def set_shape(self, npos, tile_pos, vec, batched=False, ratio=False):
+        self.calls.append((npos, tile_pos, vec, batched, ratio))
 
 
 def test_buckets():
@@ -46,7 +46,8 @@ def test_round_trip_and_apply(tmp_path):
     assert c2.get(t, 20000, True, ratio=True)["tile_pos"] == 4      # same bucket
     assert c2.apply(t, 20000, batched=True, ratio=True)
     assert c2.apply(t, 30000, batched=True)
-    assert t.calls == [(20000, 4, 4, True), (30000, 8, 2, True)]
+    # the ratio shape goes to the table's ratio mode, the plain one to the plain mode
+    assert t.calls == [(20000, 4, 4, True, True), (30000, 8, 2, True, False)]
     with open(path) as f:
         assert json.load(f) == c2.entries
 
