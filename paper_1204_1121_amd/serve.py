@@ -93,12 +93,14 @@ class Server:
 
     def offer(self, req: ServeRequest) -> None:
         """A request arrives.  Requests that can never fit are rejected now."""
-        need = self.b.request_bytes(req.system, req.npos)
         if req.system < 0 or req.system >= self.b.nsystems:
             self._finish(req, REJECTED, f"unknown system {req.system}")
-        elif req.npos < 1:
+            return
+        if req.npos < 1:
             self._finish(req, REJECTED, "empty request")
-        elif need > self.budget:
+            return
+        need = self.b.request_bytes(req.system, req.npos)
+        if need > self.budget:
             self._finish(req, REJECTED, f"request needs {need} bytes, budget is {self.budget}")
         elif req.npos > self.b.capacity(req.system):
             self._finish(req, REJECTED,
@@ -294,6 +296,8 @@ class GpuBackend:
         self.sort_threshold = sort_threshold
         self._cap = capacity if batched else 1536
         self._maxr = max_requests if batched else 1
+        self.sorted_launches = 0      # launches replaying the sorted batched plan
+        self.direct_launches = 0      # launches running one blip_eval
         dev = torch.device("cuda", torch.cuda.current_device())
         self.slots = []
         for t in tables:
@@ -345,10 +349,13 @@ class GpuBackend:
             if self.batched and row >= self.sort_threshold:
                 sl["off"].copy_(hoff, non_blocking=True)
                 sl["plan"].launch(sl["stream"])
+                self.sorted_launches += 1
             elif self.batched:
                 out = tuple(x[:row] for x in sl["out"])
                 self.tables[s].eval(sl["pos"][:row], out=out, stream=sl["stream"])
+                self.direct_launches += 1
             else:
+                self.direct_launches += 1
                 out = tuple(x[:row] for x in sl["out"])
                 self.tables[s].eval(sl["pos"][:row], out=out, kernel=self.kernel,
                                     stream=sl["stream"])

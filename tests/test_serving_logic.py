@@ -35,6 +35,7 @@ class FakeBackend:
         self.fail_on = set(fail_on)     # rids whose launch raises in done()
         self.launched = []              # (system, slot, [rids], t_start)
         self.results = {}
+        self.bytes_per_pos = [100] * len(systems)
 
     def capacity(self, s):
         return self._cap
@@ -43,7 +44,10 @@ class FakeBackend:
         return self._maxr
 
     def request_bytes(self, s, npos):
-        return npos * 100
+        # per-system bytes per position, indexed like the GPU backend's
+        # tables, so a request for an unknown system must be rejected before
+        # its size is asked for
+        return npos * self.bytes_per_pos[s]
 
     def launch(self, s, slot, reqs):
         n = sum(r.npos for r in reqs)
@@ -163,11 +167,13 @@ def test_rejections():
     sv.offer(req(0, 0, 16))      # 1600 bytes > budget
     sv.offer(ServeRequest(1, 0, np.zeros((0, 3))))   # empty
     sv.offer(req(2, 5, 3))       # unknown system
+    sv.offer(req(4, -1, 3))      # unknown system
     big = FakeBackend(clock, make_systems(), capacity=20)
     sv2 = Server(big, budget_bytes=10 ** 9, clock=clock)
     sv2.offer(req(3, 0, 21))     # more positions than a launch holds
     st = {r.rid: r.status for r in sv.finished + sv2.finished}
-    assert st == {0: REJECTED, 1: REJECTED, 2: REJECTED, 3: REJECTED}
+    assert st == {0: REJECTED, 1: REJECTED, 2: REJECTED, 3: REJECTED, 4: REJECTED}
+    assert "unknown system" in [r for r in sv.finished if r.rid == 2][0].error
     assert sv.idle() and sv2.idle()
 
 
