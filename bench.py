@@ -506,7 +506,7 @@ def tune_ratio_pass(wk, table, npos, stream):
     found = []
     for P in (1, 2, 4, 8, 16):
         for o in (1, 2, 4):
-            table.set_shape(npos, P, o, batched=True)
+            table.set_shape(npos, P, o, batched=True, ratio=True)
             wk.ratio_values(tr, outs)
             torch.cuda.synchronize()
             ev[0].record(stream)
@@ -516,7 +516,7 @@ def tune_ratio_pass(wk, table, npos, stream):
             torch.cuda.synchronize()
             found.append({"tile_pos": P, "vec": o, "us": ev[0].elapsed_time(ev[1]) * 100.0})
     best = min(found, key=lambda e: e["us"])
-    table.set_shape(npos, best["tile_pos"], best["vec"], batched=True)
+    table.set_shape(npos, best["tile_pos"], best["vec"], batched=True, ratio=True)
     return best
 
 
@@ -529,7 +529,7 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
     local kinetic energy), with the time of each phase.
 
     Statistics (the paper's comparison of quasi-simultaneous and
-    configuration-by-configuration updating, Table energy_eval, on a
+    particle-by-particle updating, Eq. (11.12.23.0b) and Table energy_eval, on a
     synthetic system): 64 walkers of 2 x 8 electrons on a small table,
     both chains from the same start, acceptance and mean local kinetic energy
     with the standard error over the independent walkers."""
@@ -607,7 +607,7 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
 
     if args.no_vmc_stats:
         return res
-    # -- statistics: quasi-simultaneous against configuration-by-configuration
+    # -- statistics: quasi-simultaneous against particle-by-particle
     A = np.array([[6.0, 0.3, 0.0], [0.2, 5.0, 0.4], [0.0, -0.3, 5.5]])
     ng, Ls, Ws = (12, 11, 10), 8, 64
     rng = np.random.default_rng(wl.SEED_BASE + 12)
@@ -615,7 +615,7 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
     ts = blip.Table(A, ng, coef, "f32")
     start = torch.from_numpy(rng.uniform(0, 1, (Ws, 2 * Ls, 3)) @ A).cuda()
     chains = {"quasi_simultaneous": vmc.Walkers(ts, start.clone(), stream=stream),
-              "configuration_by_configuration": vmc.Walkers(ts, start.clone(), stream=stream)}
+              "particle_by_particle": vmc.Walkers(ts, start.clone(), stream=stream)}
     nequil, nsample, sig = 200, 1000, 0.3
     nrec, wrec = (100, 8) if leg is not None else (0, 0)   # steps replayed on the oracle
     rec = {"eta": [], "uni": [], "e": [], "acc": []}
@@ -662,7 +662,7 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
                        "seconds": time.perf_counter() - t0}
         if name == "quasi_simultaneous":
             stats[name]["min_sequential_ratio"] = float(seq_min.item())
-    q, c = stats["quasi_simultaneous"], stats["configuration_by_configuration"]
+    q, c = stats["quasi_simultaneous"], stats["particle_by_particle"]
     diff = q["mean_kinetic_hartree"] - c["mean_kinetic_hartree"]
     err = float(np.hypot(q["stderr"], c["stderr"]))
     stats["difference_in_stderr"] = diff / err

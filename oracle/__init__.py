@@ -18,7 +18,7 @@ Two independent formulations live here:
 * :mod:`oracle.slater` -- the sequential Sherman-Morrison update of the
   inverse Slater matrix after accepted moves, in NumPy.
 * :mod:`oracle.vmc` -- Monte Carlo steps on a synthetic Slater determinant:
-  a quasi-simultaneous step and a configuration-by-configuration sweep.
+  a quasi-simultaneous step and a particle-by-particle sweep.
 
 Inputs are NumPy arrays; outputs are float64 (complex128 for complex tables).
 """

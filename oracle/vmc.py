@@ -13,9 +13,10 @@ accept/reject decision, then the local energy (here the kinetic part,
   *old* configuration; the accepted ones are then applied, the inverse
   Slater matrices brought up to date one accepted electron at a time in
   electron order (Sec. VI.D).
-* :func:`pbp_sweep` -- the configuration-by-configuration reference the
-  paper compares with: the same proposals, applied one electron at a time,
-  each judged against the configuration holding all earlier decisions.
+* :func:`pbp_sweep` -- the particle-by-particle (sequential) updating the
+  paper compares with (Eq. (11.12.23.0b)): the same proposals, applied one
+  electron at a time, each judged against the configuration holding all
+  earlier decisions.
 
 Random numbers are inputs: eta[j] (Gaussian displacements, bohr) and
 uniform[j] in [0, 1).  A move is accepted when uniform < ratio^2.

@@ -172,7 +172,7 @@ class Walkers:
         return self.e_kin
 
     def pbp_sweep(self, eta: torch.Tensor, uniform: torch.Tensor, energy: bool = True):
-        """The configuration-by-configuration comparison: electron g of every
+        """The particle-by-particle comparison (Eq. (11.12.23.0b)): electron g of every
         walker moves alone, g = 0 .. 2n-1, each judged against the state that
         holds the earlier decisions (one masked step per electron; for
         comparisons on small systems, not a fast path)."""

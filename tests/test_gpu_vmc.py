@@ -1,4 +1,4 @@
-"""Quasi-simultaneous and configuration-by-configuration Monte Carlo steps on
+"""Quasi-simultaneous and particle-by-particle Monte Carlo steps on
 the GPU (paper_1204_1121_amd/vmc.py) against the FP64 oracle (oracle/vmc.py)
 with the same random numbers.
 

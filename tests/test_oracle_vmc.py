@@ -1,7 +1,7 @@
 """Pins of the oracle's Monte Carlo steps (oracle/vmc.py) by determinants and
 inverses computed with numpy.linalg on the Slater matrices themselves, by
 finite differences of the determinant for the kinetic energy, and by the
-special cases where quasi-simultaneous and configuration-by-configuration
+special cases where quasi-simultaneous and particle-by-particle
 updating must coincide."""
 import zlib
 
