@@ -23,6 +23,41 @@ def group_errors(gpu: dict, ref: dict) -> dict:
     return {k: rel(gpu[k], ref[k]) for k in ref if gpu.get(k) is not None}
 
 
+ELEM_FLOOR = 1e-3
+
+
+def elem_rel(y, ref) -> np.ndarray:
+    """Elementwise relative error |y - y*| / (|y*| + 1e-3 max|y*|) of every
+    element of a component group (the floor keeps elements near a node of
+    the orbital from dividing by ~0)."""
+    y = np.asarray(y)
+    ref = np.asarray(ref)
+    if ref.size == 0:
+        return np.zeros(0)
+    den = np.abs(ref) + ELEM_FLOOR * float(np.max(np.abs(ref)))
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(y - ref) / den
+
+
+def error_report(gpu: dict, ref: dict) -> dict:
+    """Per component group: the normwise error, and the 99th percentile and
+    maximum of the elementwise error."""
+    out = {}
+    for k in ref:
+        if gpu.get(k) is None:
+            continue
+        e = elem_rel(gpu[k], ref[k])
+        out[k] = {"norm": rel(gpu[k], ref[k]),
+                  "elem_p99": float(np.percentile(e, 99)) if e.size else 0.0,
+                  "elem_max": float(np.max(e)) if e.size else 0.0}
+    return out
+
+
+def format_report(rep: dict) -> str:
+    return " ".join(f"{k}: norm {v['norm']:.2e} p99 {v['elem_p99']:.2e} max {v['elem_max']:.2e}"
+                    for k, v in rep.items())
+
+
 def to_np(t):
     return None if t is None else t.detach().cpu().numpy()
 

@@ -14,8 +14,8 @@ import torch
 
 import oracle
 from paper_1204_1121_amd import workloads as wl
-from tests.gpu_util import (group_errors, quantize_bf16, quantize_f16_scaled, say,
-                            to_np)
+from tests.gpu_util import (error_report, format_report, quantize_bf16,
+                            quantize_f16_scaled, say, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,12 +41,16 @@ def gpu_eval(table, pos, grad=True, **kw):
     return {"val": to_np(v), "grad": to_np(g), "lap": to_np(l)}
 
 
-def check(gpu, ref, tol, label):
-    e = group_errors(gpu, ref)
-    say(f"  {label}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-    for k, v in e.items():
-        assert v <= tol, (label, k, v)
-    return e
+def check(gpu, ref, tol, label, elem=None):
+    """Normwise error <= tol per component group; with ``elem``, also the
+    99th percentile of the elementwise error <= elem.  Both are printed."""
+    rep = error_report(gpu, ref)
+    say(f"  {label}: {format_report(rep)}")
+    for k, v in rep.items():
+        assert v["norm"] <= tol, (label, k, v)
+        if elem is not None:
+            assert v["elem_p99"] <= elem, (label, k, v)
+    return {k: v["norm"] for k, v in rep.items()}
 
 
 # ---------------------------------------------------------------------------
