@@ -189,6 +189,30 @@ BLIP_API int blip_eval_batched(blip_table t, const double* pos, const int64_t* o
 BLIP_API int blip_workspace_size(blip_table t, int64_t capacity, size_t* bytes);
 
 /*
+ * blip_eval_batched_static -- blip_eval_batched without a workspace argument
+ * and without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The sort workspace lives in a fixed 4.5 MiB device array inside
+ * the library, one per device, held until the process ends; its device
+ * address is looked up once per device on the first call with that device
+ * current.
+ *
+ *  t, pos, offsets, nw, val, grad, lap, stream: as blip_eval_batched.
+ *  capacity  as blip_eval_batched, at most 131,072 positions (BLIP_E_ARG
+ *            beyond; the 4.5 MiB covers the sort of that many positions on
+ *            any table).
+ * Results equal blip_eval_batched's bit for bit (the same kernels and launch
+ * shape).  Every call on a device shares that device's array and the kernels
+ * clear what must start at zero, so consecutive calls need nothing from the
+ * caller; calls that overlap on one device (different streams, or host
+ * threads racing to enqueue) race on the array and must be serialised by the
+ * caller, e.g. on one stream.  No hipMalloc, hipFree or memset.
+ */
+BLIP_API int blip_eval_batched_static(blip_table t, const double* pos, const int64_t* offsets,
+                                      int nw, int64_t capacity, void* val, void* grad, void* lap,
+                                      void* stream);
+
+/*
  * Plans: blip_eval_batched captured once into a HIP graph on fixed buffers,
  * then replayed with one hipGraphLaunch.  Between launches the caller may
  * rewrite the contents of pos and offsets (the device-side total may change

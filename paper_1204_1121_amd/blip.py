@@ -64,6 +64,8 @@ def lib() -> ctypes.CDLL:
     L.blip_eval_ex.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.POINTER(EvalOpts), vp]
     L.blip_eval_batched.restype = ci
     L.blip_eval_batched.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.blip_eval_batched_static.restype = ci
+    L.blip_eval_batched_static.argtypes = [vp, vp, vp, ci, i64, vp, vp, vp, vp]
     L.blip_workspace_size.restype = ci
     L.blip_workspace_size.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
     L.blip_plan_create.restype = ci
@@ -363,6 +365,20 @@ class Table:
                                       int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
                                       _ptr(lap), _ptr(workspace), workspace.numel(),
                                       _stream_ptr(stream)))
+        return val, g, lap
+
+    def eval_batched_static(self, pos: torch.Tensor, offsets: torch.Tensor, out,
+                            capacity: int | None = None, stream=None):
+        """blip_eval_batched_static: the batched launch with the library's
+        fixed scratch; out = (val, grad, lap) preallocated by the caller
+        (grad = lap = None for values only).  Nothing is allocated."""
+        if offsets.dtype != torch.int64 or not offsets.is_cuda:
+            raise ValueError("offsets must be a CUDA int64 tensor [nw+1]")
+        cap = pos.shape[0] if capacity is None else int(capacity)
+        val, g, lap = out
+        check(lib().blip_eval_batched_static(self.handle, _ptr(pos), _ptr(offsets),
+                                             int(offsets.shape[0]) - 1, cap, _ptr(val), _ptr(g),
+                                             _ptr(lap), _stream_ptr(stream)))
         return val, g, lap
 
     def plan(self, pos, offsets, out, workspace, capacity: int | None = None) -> "Plan":

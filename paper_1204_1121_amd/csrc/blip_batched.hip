@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "blip_runtime.hpp"
@@ -307,6 +308,49 @@ static int ratio_batched(blip_table t, const double* pos, const int64_t* offsets
                            &ra);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch for blip_eval_batched_static: the sort workspace of the
+// batched launch held in a file-scope device array, so that callers which
+// cannot allocate device memory still get the sorted persistent launch.
+// Each device holds its own copy of the array until the process ends.
+//
+// In host code `scratch` names a host-side stand-in, not device memory:
+// host code only ever uses the address hipGetSymbolAddress returns for the
+// current device, kept per device in scratch_dev.
+constexpr int64_t kStaticCapacity = 131072;       // positions per call at most
+constexpr size_t kScratchBytes = 4608u << 10;      // 4.5 MiB >= the layout at that capacity
+static __device__ __align__(256) char scratch[kScratchBytes];
+// the sort layout at the largest capacity and brick count, with its five
+// 256-byte alignment pads, fits the array
+static_assert(kStaticCapacity * (2 * sizeof(int) + 3 * sizeof(double)) +
+                  2 * sizeof(int) * (kMaxBins + 8) + 5 * 256 <= kScratchBytes,
+              "fixed scratch too small for its stated capacity");
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex scratch_mu;
+static void* scratch_dev[kMaxScratchDevices];
+
+// The device address of `scratch` on device dev (the current device),
+// looked up once per device.
+static int scratch_address(int dev, void** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(BLIP_E_ARG, "device %d beyond the %d devices the fixed scratch serves", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[dev] == nullptr) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (p == nullptr || (reinterpret_cast<uintptr_t>(p) & 255u) != 0)
+            return fail(BLIP_E_HIP, "fixed scratch on device %d is not 256-byte aligned", dev);
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return BLIP_OK;
+}
+
 }  // namespace blip
 
 struct blip_plan_s {
@@ -341,6 +385,38 @@ BLIP_API int blip_eval_batched(blip_table t, const double* pos, const int64_t* o
     int P, OE;
     batched_shape(t, capacity, P, OE);
     return enqueue_batched(t, pos, offsets, nw, capacity, val, grad, lap, workspace, P, OE,
+                           static_cast<hipStream_t>(stream));
+}
+
+BLIP_API int blip_eval_batched_static(blip_table t, const double* pos, const int64_t* offsets,
+                                      int nw, int64_t capacity, void* val, void* grad, void* lap,
+                                      void* stream)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (nw < 0) return fail(BLIP_E_ARG, "nw must be >= 0 (got %d)", nw);
+    if (capacity < 0) return fail(BLIP_E_ARG, "capacity must be >= 0");
+    if (nw == 0 || capacity == 0) return BLIP_OK;
+    if (capacity > kStaticCapacity)
+        return fail(BLIP_E_ARG, "capacity %lld exceeds the fixed scratch's %lld positions",
+                    (long long)capacity, (long long)kStaticCapacity);
+    const size_t need = sort_layout(t, capacity).total;
+    if (need > kScratchBytes)
+        return fail(BLIP_E_ARG, "the sort of %lld positions needs %zu bytes of scratch (%zu fixed)",
+                    (long long)capacity, need, kScratchBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != t->device)
+        return fail(BLIP_E_STATE, "table lives on device %d but device %d is current", t->device,
+                    dev);
+    void* ws = nullptr;
+    int rc = scratch_address(dev, &ws);
+    if (rc != BLIP_OK) return rc;
+    rc = check_batched_args(t, pos, offsets, nw, capacity, val, grad, lap, ws, kScratchBytes);
+    if (rc != BLIP_OK) return rc;
+    int P, OE;
+    batched_shape(t, capacity, P, OE);
+    return enqueue_batched(t, pos, offsets, nw, capacity, val, grad, lap, ws, P, OE,
                            static_cast<hipStream_t>(stream));
 }
 

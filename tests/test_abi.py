@@ -93,6 +93,8 @@ def test_eval_rejects_bad_handle(blip):
     junk = (ctypes.c_uint32 * 64)()
     rc = L.blip_eval(ctypes.cast(junk, ctypes.c_void_p), None, 1, None, None, None, None)
     assert rc == -6
+    rc = L.blip_eval_batched_static(None, None, None, 1, 1, None, None, None, None)
+    assert rc == -6
     assert L.blip_free(None) == 0
 
 
