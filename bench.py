@@ -70,6 +70,41 @@ def distinct_rows(lattice, n, pos) -> int:
     return int(np.unique(rows.reshape(-1)).size)
 
 
+ELEM_FLOOR = 1e-3
+
+
+def error_figures(got: dict, ref: dict) -> dict:
+    """Per component group (val, grad, lap): the normwise error
+    max|y - y*| / max|y*| over the group, and the 99th percentile and maximum
+    of the elementwise error |y - y*| / (|y*| + 1e-3 max|y*|) (the floor keeps
+    elements next to a node of an orbital from dividing by ~0)."""
+    out = {}
+    for k, r in ref.items():
+        g = got.get(k)
+        if g is None or r is None:
+            continue
+        r = np.asarray(r)
+        d = np.abs(np.asarray(g) - r)
+        mx = float(np.max(np.abs(r))) if r.size else 0.0
+        den = np.abs(r) + ELEM_FLOOR * mx
+        e = d / np.where(den > 0, den, 1.0)
+        out[k] = {"norm": float(np.max(d)) / mx if mx > 0 else float(np.max(d, initial=0.0)),
+                  "elem_p99": float(np.percentile(e, 99)) if e.size else 0.0,
+                  "elem_max": float(np.max(e)) if e.size else 0.0}
+    return out
+
+
+def merge_errors(reps) -> dict:
+    """Worst case over several error_figures reports."""
+    out = {}
+    for rep in reps:
+        for k, v in rep.items():
+            cur = out.setdefault(k, {"norm": 0.0, "elem_p99": 0.0, "elem_max": 0.0})
+            for f in cur:
+                cur[f] = max(cur[f], v[f])
+    return out
+
+
 def time_region(fn, blocks, steps, warmup, stream):
     """The timed region: warmup untimed steps, then exactly `steps` steps
     bracketed by synchronisation, with one HIP event pair on the launch
@@ -114,6 +149,44 @@ def time_launches(fn, blocks, steps, warmup, stream, pre=None):
     return wall, durs
 
 
+def cpu_description() -> str:
+    """The host CPU as lscpu names it: model name, family/model/stepping,
+    sockets x cores x threads (a virtual machine may report a generic model
+    name; the family and model numbers still identify the part)."""
+    import subprocess
+    f = {}
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not f.get("Model name"):
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        f["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    parts = [f.get("Model name", "unknown CPU")]
+    zen = {"23": "Zen/Zen 2", "25": "Zen 3/Zen 4", "26": "Zen 5"}
+    if f.get("Vendor ID") == "AuthenticAMD" and f.get("CPU family") in zen:
+        parts.append(zen[f["CPU family"]])
+    fam = [f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if f.get(k)]
+    if fam:
+        parts.append("(" + ", ".join(fam) + ")")
+    if f.get("Socket(s)") and f.get("Core(s) per socket"):
+        parts.append(f"{f['Socket(s)']} socket(s) x {f['Core(s) per socket']} cores x "
+                     f"{f.get('Thread(s) per core', '1')} threads")
+    if f.get("CPU max MHz"):
+        parts.append(f"max {float(f['CPU max MHz']):.0f} MHz")
+    return ", ".join(parts)
+
+
 class CpuBaselineLeg:
     """The CPU-baseline leg: every use of the FP64 oracle in this file goes
     through this object (timings of the oracle on the host cores, and the FP64
@@ -126,15 +199,7 @@ class CpuBaselineLeg:
         self.oracle = oracle
         self.slater = slater
         self.threads = len(os.sched_getaffinity(0))
-        self.cpu_model = ""
-        try:
-            with open("/proc/cpuinfo") as f:
-                for line in f:
-                    if line.startswith("model name"):
-                        self.cpu_model = line.split(":", 1)[1].strip()
-                        break
-        except OSError:
-            pass
+        self.cpu_model = cpu_description()
 
     def replay_qs(self, lattice, n_grid, coef, start, etas, unis):
         """The oracle's own FP64 chain of quasi-simultaneous steps from the
@@ -180,6 +245,31 @@ class CpuBaselineLeg:
                           f"{self.threads} threads",
                 "single_core": {"value": npos * L / dt_one, "unit": UNIT, "cores": 1,
                                 "sample": f"one block of {npos} positions: {dt_one:.2f} s"}}
+
+    def positions(self, spec, coef, pos, budget_s=8.0, what=""):
+        """FP64 oracle on a bounded prefix of the positions pos (val+grad+lap):
+        all host cores for about budget_s, and up to 256 positions on one
+        core.  Returns a cpu_baseline record in orbital evals/s."""
+        L = spec.norb
+        probe = pos[: min(len(pos), 256)]
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, probe, kvec=spec.kvec,
+                             nthreads=self.threads)
+        rate = len(probe) / max(time.perf_counter() - t0, 1e-6)
+        n = int(max(len(probe), min(len(pos), rate * budget_s)))
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, pos[:n], kvec=spec.kvec,
+                             nthreads=self.threads)
+        dt = max(time.perf_counter() - t0, 1e-6)
+        t0 = time.perf_counter()
+        self.oracle.evaluate(spec.lattice, spec.n, coef, probe, kvec=spec.kvec, nthreads=1)
+        dt1 = max(time.perf_counter() - t0, 1e-6)
+        return {"value": n * L / dt, "unit": UNIT, "cores": self.threads, "kind": "oracle",
+                "cpu": self.cpu_model,
+                "sample": f"the first {n} of {len(pos)} positions{what} x {L} orbitals, "
+                          f"val+grad+lap, FP64: {dt:.1f} s on {self.threads} threads",
+                "single_core": {"value": len(probe) * L / dt1, "unit": UNIT, "cores": 1,
+                                "sample": f"{len(probe)} positions: {dt1:.2f} s"}}
 
     def reference(self, spec, coef, pos, want=("val", "grad", "lap")):
         """FP64 oracle values at pos (all host cores)."""
@@ -270,7 +360,7 @@ def bench_sm(args, leg=None):
     return res
 
 
-def bench_batched(table, spec, args, nbatch=4):
+def bench_batched(table, spec, args, nbatch=4, leg=None, coef=None):
     """512 walkers with move blocks of U[1,256] positions on the same table:
     one sorted persistent launch per batch (replayed hipGraph plan), against
     the plain kernel on the concatenation and per-walker launch loops."""
@@ -336,6 +426,13 @@ def bench_batched(table, spec, args, nbatch=4):
     res["speedup_vs_plain_concatenated"] = res["plain_concatenated_us"] / res["launch_us"]
     for pl in plans:
         pl.free()
+    if leg is not None and coef is not None:
+        cb = leg.positions(spec, coef, bs[0].pos, what=" of the first batch (walkers in order)")
+        cb["gpu_speedup_vs_threads"] = res["value"] / cb["value"]
+        cb["gpu_speedup_vs_one_core"] = res["value"] / cb["single_core"]["value"]
+        res["cpu_baseline"] = cb
+        log(f"batched oracle: {cb['value']:.3e} evals/s on {cb['cores']} threads, "
+            f"{cb['single_core']['value']:.3e} on one core")
     log(f"batched: {t_b * 1e6:.0f} us per 512-walker batch; plain(concat) "
         f"{res['plain_concatenated_us']:.0f} us; per-walker plain loop {res['per_walker_plain_us']:.0f} us")
     return res
@@ -377,7 +474,7 @@ def bench_block_sizes(table, spec, stream, cache, args, sizes=(1, 8, 64, 256, 15
     return rows
 
 
-def bench_serving(args):
+def bench_serving(args, leg=None):
     """Three resident systems (the 768-orbital table; 48^3 x 256; 96x96x64 x
     1024), requests of 1..1536 positions (log-uniform) arriving by Poisson
     process at rates swept around the saturated rate; continuous batching
@@ -388,10 +485,12 @@ def bench_serving(args):
     from paper_1204_1121_amd.serve import GpuBackend, Server, ServeRequest
     specs = wl.spec_serving()
     t0 = time.perf_counter()
-    tables = []
+    tables, coefs = [], []
     for sp in specs:
         c = wl.coefficients(sp)
         tables.append(blip.Table(sp.lattice, sp.n, c, "f32"))
+        if leg is not None:
+            coefs.append(c)            # the oracle's copy of the served tables
         del c
     resident = sum(t.info()["device_bytes"] for t in tables)
     log(f"serving: {len(tables)} tables, {resident / 1e9:.2f} GB resident "
@@ -399,9 +498,10 @@ def bench_serving(args):
     norb = [sp.norb for sp in specs]
     nreq = args.serve_requests
 
-    def make(rate, seed, n=nreq):
+    def make(rate, seed, n=nreq, keep_every=0):
         rq = wl.serving_requests(len(specs), n, rate=rate, specs=specs, seed=seed)
-        return [ServeRequest(r.rid, r.system, r.pos, arrival=r.arrival) for r in rq]
+        return [ServeRequest(r.rid, r.system, r.pos, arrival=r.arrival,
+                             keep=keep_every > 0 and r.rid % keep_every == 0) for r in rq]
 
     def run(backend, budget, reqs):
         sv = Server(backend, budget_bytes=budget)
@@ -429,6 +529,8 @@ def bench_serving(args):
     small = run(be, 64 << 20, make(0.9 * rate_sat, 300))
     small["budget_bytes"] = 64 << 20
     out["small_budget_0.9x"] = small
+    if leg is not None:
+        out["oracle_check"] = serving_oracle_check(leg, be, specs, coefs, make, run)
     be.close()
     # unbatched baseline: one request per launch, plain single-block kernel
     bp = GpuBackend(tables, batched=False, kernel="plain")
@@ -446,13 +548,101 @@ def bench_serving(args):
     return out
 
 
+def serving_oracle_check(leg, be, specs, coefs, make, run, every=50):
+    """The saturated run's request stream served again with one result in
+    `every` copied back, each compared with the FP64 oracle (normwise and
+    elementwise, per component group and system), and the oracle's time per
+    position on those requests (all host cores, and one core)."""
+    reqs = make(1e9, 100, keep_every=every)
+    run(be, 2 << 30, reqs)
+    reqs = [r for r in reqs if r.keep and r.status == "done"]
+    per_sys, npos_sys, dt_sys = {}, {}, {}
+    for r in reqs:
+        sp = specs[r.system]
+        t0 = time.perf_counter()
+        ref = leg.oracle.evaluate(sp.lattice, sp.n, coefs[r.system], r.pos,
+                                  nthreads=leg.threads)
+        dt_sys[sp.name] = dt_sys.get(sp.name, 0.0) + time.perf_counter() - t0
+        npos_sys[sp.name] = npos_sys.get(sp.name, 0) + r.npos
+        per_sys.setdefault(sp.name, []).append(error_figures(r.result, ref))
+    res = {"requests_checked": len(reqs), "every": every,
+           "errors_by_system": {k: merge_errors(v) for k, v in per_sys.items()},
+           "errors": merge_errors([e for v in per_sys.values() for e in v]),
+           "oracle_us_per_position": {k: dt_sys[k] / npos_sys[k] * 1e6 for k in dt_sys},
+           "oracle_threads": leg.threads}
+    one = {}
+    for s_idx, sp in enumerate(specs):
+        pos = next((r.pos for r in reqs if r.system == s_idx), None)
+        if pos is None:
+            continue
+        pos = pos[:64]
+        t0 = time.perf_counter()
+        leg.oracle.evaluate(sp.lattice, sp.n, coefs[s_idx], pos, nthreads=1)
+        one[sp.name] = (time.perf_counter() - t0) / len(pos) * 1e6
+    res["oracle_us_per_position_one_core"] = one
+    worst = res["errors"]
+    log("serving oracle check: " + f"{len(reqs)} requests, " +
+        " ".join(f"{k} {v['norm']:.1e} (p99 elem {v['elem_p99']:.1e})" for k, v in worst.items()))
+    return res
+
+
+def bench_shard_shape(args, coef, spec, cache, full_us, leg=None, shards=8):
+    """One GPU's share of the table sharded by orbitals over `shards` GPUs:
+    the first 768/shards orbitals of the 768-orbital table on the same
+    72x72x48 grid, evaluated at the same 1,536-position blocks with the
+    tuned kernel (its own cached or autotuned shape).  B_alg counts the
+    shard's distinct rows, its outputs and the positions; the ideal is the
+    full table's launch time divided by the number of shards."""
+    import torch
+    from paper_1204_1121_amd import blip
+    from paper_1204_1121_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+    L = spec.norb // shards
+    npos = 1536
+    c = np.ascontiguousarray(coef[..., :L])
+    t = blip.Table(spec.lattice, spec.n, c, "f32")
+    o = t.alloc_outputs(npos)
+    blocks_np = [wl.move_block(spec, npos, block=b) for b in range(NROT)]
+    blocks = [torch.from_numpy(b).cuda() for b in blocks_np]
+    if args.retune or not cache.apply(t, npos):
+        best, _ = t.autotune(torch.cat(blocks).contiguous(), o, rotate=NROT)
+        cache.put(t, npos, False, best, note=f"blip_autotune rotate={NROT}")
+    P, vec = t.get_shape(npos)
+    calls = {id(b): t.bind(b, o) for b in blocks}
+    _, tk = time_region(lambda b: calls[id(b)](), blocks, max(50, min(args.steps, 200)), 10,
+                        stream)
+    U = [distinct_rows(spec.lattice, spec.n, b) for b in blocks_np]
+    b_alg = float(np.mean([u * L * 4 + npos * (5 * L * 4 + 24) for u in U]))
+    res = {"orbitals": L, "shards": shards, "npos": npos, "grid": list(spec.n),
+           "shape": {"tile_pos": P, "vec": vec}, "kernel_us": tk * 1e6,
+           "evals_per_s": npos * L / tk, "bytes_algorithmic": b_alg,
+           "roofline": {"bound": "hbm", "achieved": b_alg / tk / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": b_alg / tk / 1e9 / HBM_PEAK_GBS},
+           "full_table_kernel_us": full_us,
+           "ideal_shard_us": full_us / shards,
+           "shard_efficiency": full_us / shards / (tk * 1e6)}
+    if leg is not None:
+        ref = leg.reference(spec, c, blocks_np[0])
+        v, g, l = t.eval(blocks[0], out=o)
+        torch.cuda.synchronize()
+        got = {"val": v.cpu().numpy(), "grad": g.cpu().numpy(), "lap": l.cpu().numpy()}
+        res["errors"] = error_figures(got, ref)
+    t.free()
+    log(f"shard shape L={L}: {tk * 1e6:.1f} us per 1,536-block (P={P} o={vec}), "
+        f"{res['roofline']['frac']:.3f} of HBM peak on B_alg; full table / {shards} = "
+        f"{full_us / shards:.1f} us")
+    return res
+
+
 def bench_precision(args, real_coef, real_spec, cache, leg=None):
     """Storage dtypes at 1,536 positions: the complex k-point table (384
     orbitals) as complex64 / BF16 pairs / FP16 pairs, and the 768-orbital real
     table as FP32 / BF16 / FP16.  For each: kernel time, evals/s and the
     normwise max relative error of val, grad and lap against the FP64 oracle
     on the FP32 master, over the whole block (errors only with the CPU-baseline
-    leg, which supplies the oracle's values)."""
+    leg, which supplies the oracle's values).  Beside the normwise error, the
+    99th percentile and maximum of the elementwise error
+    |y - y*| / (|y*| + 1e-3 max|y*|) per component group."""
     import torch
     from paper_1204_1121_amd import blip
     from paper_1204_1121_amd import workloads as wl
@@ -483,10 +673,12 @@ def bench_precision(args, real_coef, real_spec, cache, leg=None):
                 v, g, l = t.eval(blocks[0], out=o)
                 torch.cuda.synchronize()
                 got = {"val": v.cpu().numpy(), "grad": g.cpu().numpy(), "lap": l.cpu().numpy()}
-                err = {k: float(np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k])))
-                       for k in ref}
-                rec["max_rel_err"] = err
-                msg = f", err val {err['val']:.1e} grad {err['grad']:.1e} lap {err['lap']:.1e}"
+                fig = error_figures(got, ref)
+                rec["max_rel_err"] = {k: f["norm"] for k, f in fig.items()}
+                rec["elementwise_rel_err"] = {k: {"p99": f["elem_p99"], "max": f["elem_max"]}
+                                              for k, f in fig.items()}
+                msg = ", err " + " ".join(f"{k} {f['norm']:.1e} (p99 elem {f['elem_p99']:.1e})"
+                                          for k, f in fig.items())
             out[f"{label}_{st}"] = rec
             log(f"precision {label} {st}: {tk * 1e6:.1f} us{msg}")
             t.free()
@@ -875,6 +1067,8 @@ def main():
                     help="skip the storage-dtype / complex k-point section")
     ap.add_argument("--no-paper-sizes", action="store_true",
                     help="skip the values-only complex section at the paper's system sizes")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the one-GPU orbital-shard shape (96 of the 768 orbitals)")
     ap.add_argument("--no-vmc", action="store_true",
                     help="skip the Monte Carlo step throughput and statistics section")
     ap.add_argument("--no-vmc-stats", action="store_true",
@@ -1056,6 +1250,15 @@ def main():
         except Exception as e:
             result["precision"] = {"error": f"{type(e).__name__}: {e}"}
 
+    if not args.no_shard:
+        try:
+            result["shard_shape"] = bench_shard_shape(args, coef, spec, cache, t_kernel * 1e6,
+                                                      leg)
+            if args.save_tuning:
+                cache.save(args.save_tuning)
+        except Exception as e:
+            result["shard_shape"] = {"error": f"{type(e).__name__}: {e}"}
+
     if not args.no_vmc:
         try:
             result["vmc"] = bench_vmc(args, table, spec, leg, cache)
@@ -1074,14 +1277,14 @@ def main():
 
     if not args.no_batched:
         try:
-            result["batched"] = bench_batched(table, spec, args)
+            result["batched"] = bench_batched(table, spec, args, leg=leg, coef=coef)
         except Exception as e:            # recorded, never fatal for the main line
             result["batched"] = {"error": f"{type(e).__name__}: {e}"}
     table.free()
 
     if not args.no_serving:
         try:
-            result["serving"] = bench_serving(args)
+            result["serving"] = bench_serving(args, leg)
         except Exception as e:
             result["serving"] = {"error": f"{type(e).__name__}: {e}"}
 
