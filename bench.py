@@ -504,6 +504,7 @@ def bench_serving(args, leg=None):
                              keep=keep_every > 0 and r.rid % keep_every == 0) for r in rq]
 
     def run(backend, budget, reqs):
+        backend.launch_host_s = 0.0
         sv = Server(backend, budget_bytes=budget)
         st = sv.run(reqs)
         ev = sum(r.npos * norb[r.system] for r in reqs if r.status == "done")
@@ -523,8 +524,10 @@ def bench_serving(args, leg=None):
         st["offered_fraction"] = f
         st["offered_req_per_s"] = f * rate_sat
         sweep.append(st)
-        log(f"  rate {f:.2f}x: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
-            f"{st['evals_per_s']:.3e} evals/s")
+        log(f"  rate {f:.2f}x: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms "
+            f"(queue wait p50 {st.get('queue_wait_p50_ms', 0):.3f}, in service p50 "
+            f"{st.get('in_service_p50_ms', 0):.3f} ms, host {st.get('launch_host_us_mean', 0):.1f} "
+            f"us per launch) {st['evals_per_s']:.3e} evals/s")
     out["sweep"] = sweep
     small = run(be, 64 << 20, make(0.9 * rate_sat, 300))
     small["budget_bytes"] = 64 << 20

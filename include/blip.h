@@ -227,6 +227,34 @@ BLIP_API int blip_plan_launch(blip_plan p, void* stream);
 BLIP_API int blip_plan_free(blip_plan p);
 
 /*
+ * blip_submit -- one launch of a serving loop in one call: the requests'
+ * positions (the moved electrons of several walkers, each an independent
+ * evaluation, Sec. IV.A, Eq. (11.12.23.1)) are copied from host memory to
+ * the launch's device buffer, evaluated, and an event is recorded, all on
+ * stream, so that a scheduler pays one library call per launch.
+ *
+ *  plan == NULL: copy npos positions host_pos -> dev_pos, then blip_eval_ex
+ *            (opts; NULL = the tuned kernel) on dev_pos with outputs
+ *            val/grad/lap of at least npos rows.  host_off, noff, dev_off
+ *            are ignored.
+ *  plan != NULL: the plan's graph (blip_plan_create) on its own buffers:
+ *            dev_pos and dev_off must be the buffers the plan captured,
+ *            npos <= its capacity, and noff its nw + 1 offsets (host_off,
+ *            offsets[nw] the total) are copied to dev_off before the replay;
+ *            opts must be NULL and val/grad/lap are ignored (the plan's).
+ *  host_pos  host double[npos][3]; pinned memory (hipHostMalloc) makes the
+ *            copy asynchronous, and must then stay unchanged until event
+ *            (or the stream) has completed; pageable memory is copied
+ *            before the call returns.
+ *  event     hipEventRecord'ed on stream after the launch (NULL: none).
+ * Argument errors are returned before anything is enqueued.  No allocation.
+ */
+BLIP_API int blip_submit(blip_table t, blip_plan plan, const blip_eval_opts* opts,
+                         const double* host_pos, int64_t npos, double* dev_pos,
+                         const int64_t* host_off, int noff, int64_t* dev_off, void* val,
+                         void* grad, void* lap, void* stream, void* event);
+
+/*
  * blip_autotune -- time every launch shape (P positions per workgroup x o
  * table elements per lane) on the caller's buffers and keep the fastest for
  * this table and this size bucket (npos in [2^k, 2^(k+1))).  offsets == NULL

@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.blip_plan_launch.argtypes = [vp, vp]
     L.blip_plan_free.restype = ci
     L.blip_plan_free.argtypes = [vp]
+    L.blip_submit.restype = ci
+    L.blip_submit.argtypes = [vp, vp, vp, vp, i64, vp, vp, ci, vp, vp, vp, vp, vp, vp]
     L.blip_autotune.restype = ci
     L.blip_autotune.argtypes = [vp, vp, vp, ci, i64, ci, vp, vp, vp, vp, ctypes.c_size_t, vp,
                                 ctypes.POINTER(TuneResult), ci, ctypes.POINTER(ci),
@@ -441,6 +443,46 @@ class Table:
             self.free()
         except Exception:
             pass
+
+
+class Submitter:
+    """blip_submit on fixed buffers: pinned host staging of positions (and
+    offsets), the device buffers they are copied to, the outputs, an optional
+    plan captured on those buffers, a stream and an event, with the ctypes
+    arguments built once, so one launch of a serving loop is one library
+    call.  event is a torch.cuda.Event already recorded once (so that it has
+    a HIP handle)."""
+
+    def __init__(self, table: Table, host_pos: torch.Tensor, dev_pos: torch.Tensor, out,
+                 stream, event, plan: "Plan | None" = None, host_off=None, dev_off=None,
+                 kernel: str = "auto"):
+        if not host_pos.is_pinned():
+            raise ValueError("host_pos must be pinned host memory")
+        if not event.cuda_event:
+            raise ValueError("record the event once before building a Submitter")
+        val, g, lap = out
+        self._fn = lib().blip_submit
+        self._opts = (None if kernel == "auto"
+                      else ctypes.byref(EvalOpts(KERNEL[kernel], 0, 0)))
+        self._h = table.handle
+        self._plan = plan._h if plan is not None else None
+        self._hpos, self._dpos = _ptr(host_pos), _ptr(dev_pos)
+        self._hoff, self._doff = _ptr(host_off), _ptr(dev_off)
+        self._noff = 0 if host_off is None else int(host_off.shape[0])
+        self._out = (_ptr(val), _ptr(g), _ptr(lap))
+        self._stream = _stream_ptr(stream)
+        self._event = ctypes.c_void_p(event.cuda_event)
+        self._keep = (table, host_pos, dev_pos, out, plan, host_off, dev_off, event)
+
+    def __call__(self, npos: int, use_plan: bool = False) -> None:
+        if use_plan:
+            rc = self._fn(self._h, self._plan, None, self._hpos, npos, self._dpos, self._hoff,
+                          self._noff, self._doff, None, None, None, self._stream, self._event)
+        else:
+            rc = self._fn(self._h, None, self._opts, self._hpos, npos, self._dpos, None, 0, None,
+                          *self._out, self._stream, self._event)
+        if rc != 0:
+            raise BlipError(rc, lib().blip_last_error().decode())
 
 
 class Plan:

@@ -358,6 +358,10 @@ struct blip_plan_s {
     blip_table table;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    const double* pos;       // the captured buffers (blip_submit checks them)
+    const int64_t* offsets;
+    int nw;
+    int64_t capacity;
 };
 
 using namespace blip;
@@ -486,7 +490,7 @@ BLIP_API int blip_plan_create(blip_table t, const double* pos, const int64_t* of
         (void)hipGraphDestroy(g);
         return fail_hip(e, "hipGraphInstantiate");
     }
-    auto* p = new blip_plan_s{kPlanMagic, t, g, x};
+    auto* p = new blip_plan_s{kPlanMagic, t, g, x, pos, offsets, nw, capacity};
     *out = p;
     return BLIP_OK;
 }
@@ -497,6 +501,57 @@ BLIP_API int blip_plan_launch(blip_plan p, void* stream)
     if (!table_ok(p->table)) return fail(BLIP_E_STATE, "the plan's table has been freed");
     hipError_t e = hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    return BLIP_OK;
+}
+
+BLIP_API int blip_submit(blip_table t, blip_plan plan, const blip_eval_opts* opts,
+                         const double* host_pos, int64_t npos, double* dev_pos,
+                         const int64_t* host_off, int noff, int64_t* dev_off, void* val,
+                         void* grad, void* lap, void* stream, void* event)
+{
+    if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
+    if (npos < 0) return fail(BLIP_E_ARG, "npos must be >= 0 (got %lld)", (long long)npos);
+    if (npos > 0 && (host_pos == nullptr || dev_pos == nullptr))
+        return fail(BLIP_E_ARG, "host_pos and dev_pos must be non-NULL when npos > 0");
+    if (plan != nullptr) {
+        if (plan->magic != kPlanMagic) return fail(BLIP_E_STATE, "invalid plan handle");
+        if (plan->table != t) return fail(BLIP_E_ARG, "the plan belongs to another table");
+        if (opts != nullptr) return fail(BLIP_E_ARG, "a plan's launch shape is fixed: opts must be NULL");
+        if (dev_pos != plan->pos || dev_off != plan->offsets)
+            return fail(BLIP_E_ARG, "dev_pos and dev_off must be the plan's captured buffers");
+        if (npos > plan->capacity)
+            return fail(BLIP_E_ARG, "npos %lld exceeds the plan's capacity %lld", (long long)npos,
+                        (long long)plan->capacity);
+        if (noff != plan->nw + 1 || host_off == nullptr)
+            return fail(BLIP_E_ARG, "a plan needs all %d offsets from the host", plan->nw + 1);
+    } else {
+        int kind, P, OE;
+        int rc = eval_opts(t, opts, kind, P, OE);
+        if (rc != BLIP_OK) return rc;
+        rc = check_eval_args(t, dev_pos, npos, val, grad, lap);
+        if (rc != BLIP_OK) return rc;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (npos > 0) {
+        e = hipMemcpyAsync(dev_pos, host_pos, (size_t)npos * 3 * sizeof(double),
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync of the positions");
+    }
+    if (plan != nullptr) {
+        e = hipMemcpyAsync(dev_off, host_off, (size_t)noff * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync of the offsets");
+        e = hipGraphLaunch(plan->exec, s);
+        if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    } else if (npos > 0) {
+        int rc = eval_common(t, dev_pos, npos, val, grad, lap, opts, stream);
+        if (rc != BLIP_OK) return rc;
+    }
+    if (event != nullptr) {
+        e = hipEventRecord(static_cast<hipEvent_t>(event), s);
+        if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    }
     return BLIP_OK;
 }
 

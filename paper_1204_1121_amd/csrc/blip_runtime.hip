@@ -334,10 +334,11 @@ int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, vo
     return BLIP_OK;
 }
 
-int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
-                void* lap, const blip_eval_opts* opts, void* stream)
+int eval_opts(blip_table t, const blip_eval_opts* opts, int& kind, int& P, int& OE)
 {
-    int kind = KIND_TILED, P = 0, OE = 0;
+    kind = KIND_TILED;
+    P = 0;
+    OE = 0;
     if (opts) {
         if (!table_ok(t)) return fail(BLIP_E_STATE, "invalid table handle");
         if (opts->kernel < BLIP_KERNEL_AUTO || opts->kernel > BLIP_KERNEL_SITE)
@@ -358,7 +359,16 @@ int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* 
         if (kind == KIND_F64ACC && OE == 8)
             return fail(BLIP_E_ARG, "vec=8 not supported by the FP64-accumulate kernel");
     }
-    int rc = check_eval_args(t, pos, npos, val, grad, lap);
+    return BLIP_OK;
+}
+
+int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
+                void* lap, const blip_eval_opts* opts, void* stream)
+{
+    int kind, P, OE;
+    int rc = eval_opts(t, opts, kind, P, OE);
+    if (rc != BLIP_OK) return rc;
+    rc = check_eval_args(t, pos, npos, val, grad, lap);
     if (rc != BLIP_OK || npos == 0) return rc;
 
     int P0 = 0, OE0 = 0;

@@ -91,6 +91,11 @@ int launch_tiled(const blip_table_s* t, const double* pos, int64_t npos, void* v
 bool valid_oe(const blip_table_s* t, int OE);
 int check_eval_args(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
                     void* lap);
+// Kernel kind and shape overrides from blip_eval_ex options (NULL: tuned tiled).
+int eval_opts(blip_table t, const blip_eval_opts* opts, int& kind, int& P, int& OE);
+// blip_eval_ex without the C-ABI wrapper.
+int eval_common(blip_table t, const double* pos, int64_t npos, void* val, void* grad,
+                void* lap, const blip_eval_opts* opts, void* stream);
 int check_ratio_args(blip_table t, int64_t npos, const double* pos, const double* inv_rows,
                      int64_t inv_ld, const int64_t* row_of, double* ratio, double* grad_ratio,
                      double* lap_ratio);

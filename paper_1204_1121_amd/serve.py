@@ -254,9 +254,22 @@ def summarize(reqs, makespan, server=None, norb=None) -> dict:
            "positions": int(sum(r.npos for r in done)),
            "p50_ms": float(np.percentile(lat, 50) * 1e3),
            "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+    if done:
+        # where the latency goes: waiting for admission (queue), and from
+        # admission to the scheduler seeing the completion (staging, the
+        # device, and the polling lag)
+        wait = np.array([r.t_admit - r.arrival for r in done])
+        svc = np.array([r.t_done - r.t_admit for r in done])
+        out["queue_wait_p50_ms"] = float(np.percentile(wait, 50) * 1e3)
+        out["queue_wait_p99_ms"] = float(np.percentile(wait, 99) * 1e3)
+        out["in_service_p50_ms"] = float(np.percentile(svc, 50) * 1e3)
+        out["in_service_p99_ms"] = float(np.percentile(svc, 99) * 1e3)
     if server is not None:
         out["launches"] = server.launches
         out["peak_inflight_bytes"] = server.peak_inflight
+        host = getattr(server.b, "launch_host_s", None)
+        if host is not None and server.launches:
+            out["launch_host_us_mean"] = host / server.launches * 1e6
     return out
 
 
@@ -270,9 +283,10 @@ class GpuBackend:
     Each slot owns device buffers for up to ``capacity`` positions (positions,
     offsets, val/grad/lap, sort workspace), a pinned host staging buffer, its
     own stream and, for the batched mode, a hipGraph plan of
-    blip_eval_batched on those buffers.  A launch copies the packed
-    positions and offsets host-to-device on the slot's stream and replays the
-    plan; an event marks completion.
+    blip_eval_batched on those buffers.  A launch packs the requests'
+    positions into the staging buffer and makes one library call
+    (blip_submit) that copies them host-to-device on the slot's stream,
+    evaluates them (or replays the plan) and records the slot's event.
 
     Launches smaller than ``sort_threshold`` positions skip the spatial sort
     and run one direct blip_eval on the slot's buffers (the host knows the
@@ -287,6 +301,7 @@ class GpuBackend:
                  slots_per_system: int = 2, batched: bool = True, kernel: str = "auto",
                  sort_threshold: int = 4096):
         import torch
+        from .blip import Submitter
         self.torch = torch
         self.tables = tables
         self.nsystems = len(tables)
@@ -298,6 +313,7 @@ class GpuBackend:
         self._maxr = max_requests if batched else 1
         self.sorted_launches = 0      # launches replaying the sorted batched plan
         self.direct_launches = 0      # launches running one blip_eval
+        self.launch_host_s = 0.0      # host time spent in launch() (staging + submit)
         dev = torch.device("cuda", torch.cuda.current_device())
         self.slots = []
         for t in tables:
@@ -312,10 +328,16 @@ class GpuBackend:
                 hpos = torch.zeros((cap, 3), dtype=torch.float64, pin_memory=True)
                 hoff = torch.zeros(self._maxr + 1, dtype=torch.int64, pin_memory=True)
                 plan = t.plan(pos, off, out, ws, capacity=cap) if batched else None
+                ev = torch.cuda.Event()
+                ev.record(st)                    # gives the event its HIP handle
+                sub = Submitter(t, hpos, pos, out, st, ev, plan=plan, host_off=hoff,
+                                dev_off=off, kernel=kernel if not batched else "auto")
                 per.append({"stream": st, "pos": pos, "off": off, "out": out, "ws": ws,
-                            "hpos": hpos, "hoff": hoff, "plan": plan,
-                            "event": torch.cuda.Event()})
+                            "hpos": hpos, "hoff": hoff, "hpos_np": hpos.numpy(),
+                            "hoff_np": hoff.numpy(), "plan": plan, "event": ev,
+                            "submit": sub})
             self.slots.append(per)
+        torch.cuda.synchronize()
 
     def capacity(self, s):
         return self._cap
@@ -329,37 +351,27 @@ class GpuBackend:
         return int(npos) * (24 + 5 * 4 * w)
 
     def launch(self, s, slot, reqs):
-        torch = self.torch
+        t0 = time.perf_counter()
         sl = self.slots[s][slot]
-        hpos, hoff = sl["hpos"], sl["hoff"]
+        hp = sl["hpos_np"]
         # the staging buffers are reused only after this slot's previous
         # launch completed (the scheduler frees a slot on completion)
         row = 0
-        offs = [0]
         for r in reqs:
             k = r.npos
-            hpos[row:row + k].numpy()[:] = r.pos
+            hp[row:row + k] = r.pos
             row += k
-            offs.append(row)
-        hoff[: len(offs)].numpy()[:] = np.asarray(offs, dtype=np.int64)
-        if self.batched:
-            hoff[len(offs):].fill_(row)
-        with torch.cuda.stream(sl["stream"]):
-            sl["pos"][:row].copy_(hpos[:row], non_blocking=True)
-            if self.batched and row >= self.sort_threshold:
-                sl["off"].copy_(hoff, non_blocking=True)
-                sl["plan"].launch(sl["stream"])
-                self.sorted_launches += 1
-            elif self.batched:
-                out = tuple(x[:row] for x in sl["out"])
-                self.tables[s].eval(sl["pos"][:row], out=out, stream=sl["stream"])
-                self.direct_launches += 1
-            else:
-                self.direct_launches += 1
-                out = tuple(x[:row] for x in sl["out"])
-                self.tables[s].eval(sl["pos"][:row], out=out, kernel=self.kernel,
-                                    stream=sl["stream"])
-            sl["event"].record(sl["stream"])
+        sorted_plan = self.batched and row >= self.sort_threshold
+        if sorted_plan:
+            ho = sl["hoff_np"]
+            ho[0] = 0
+            ho[1:len(reqs) + 1] = np.cumsum([r.npos for r in reqs])
+            ho[len(reqs) + 1:] = row
+            self.sorted_launches += 1
+        else:
+            self.direct_launches += 1
+        sl["submit"](row, sorted_plan)
+        self.launch_host_s += time.perf_counter() - t0
         return (s, slot)
 
     def done(self, handle):

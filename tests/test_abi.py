@@ -95,6 +95,9 @@ def test_eval_rejects_bad_handle(blip):
     assert rc == -6
     rc = L.blip_eval_batched_static(None, None, None, 1, 1, None, None, None, None)
     assert rc == -6
+    rc = L.blip_submit(None, None, None, None, 1, None, None, 0, None, None, None, None, None,
+                       None)
+    assert rc == -6
     assert L.blip_free(None) == 0
 
 
