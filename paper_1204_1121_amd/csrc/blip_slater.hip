@@ -52,6 +52,12 @@ constexpr int kSmPiece = 128;       // column tiles are a multiple of this wide
 constexpr int kSmPad = kSmChunk + 1;
 constexpr int64_t kSmMaxN = 4096;
 constexpr int kSmMaxTiles = 4;      // column tiles (partial sums of V per row)
+// S (and V - E, Y) spread over the workgroup: thread t holds column t % kSmChunk
+// of the rows t / kSmChunk + kSmRG j, j < kSmEPT.
+constexpr int kSmRG = kSmThreads / kSmChunk;   // row groups
+constexpr int kSmEPT = kSmChunk / kSmRG;       // entries of S per thread
+constexpr int kSmMB = kSmChunk / 16;           // matrix-core blocks of 16 moves
+static_assert(kSmThreads % kSmChunk == 0 && kSmChunk % 16 == 0, "chunk layout");
 
 struct SmArgs {
     int n;
@@ -179,25 +185,25 @@ __device__ __forceinline__ int sm_batched_col(const SmArgs& a, int q, int ch, in
 
 // S = V[c_m][m'] of the applied chunk, the column-tile partials summed in a
 // fixed order; unused rows and columns hold the identity.  Thread t gets
-// S[t/32 + 8j][t%32], j < 4.
+// S[t/kSmChunk + kSmRG j][t%kSmChunk], j < kSmEPT.
 __device__ __forceinline__ void sm_build_s(const double* __restrict__ Pp, int n, int nct, int kp,
-                                           const int* lcolp, int tid, double (&sv)[4])
+                                           const int* lcolp, int tid, double (&sv)[kSmEPT])
 {
     const int gc = tid % kSmChunk;
     const int gr0 = tid / kSmChunk;
-    double part[4][kSmMaxTiles];
+    double part[kSmEPT][kSmMaxTiles];
     const int cq = gc < kp ? gc : kp - 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int r = gr0 + 8 * j;
+    for (int j = 0; j < kSmEPT; ++j) {
+        const int r = gr0 + kSmRG * j;
         const int row = lcolp[r < kp ? r : kp - 1];
 #pragma unroll
         for (int t = 0; t < kSmMaxTiles; ++t)
             part[j][t] = Pp[((int64_t)(t < nct ? t : nct - 1) * n + row) * kSmChunk + cq];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int r = gr0 + 8 * j;
+    for (int j = 0; j < kSmEPT; ++j) {
+        const int r = gr0 + kSmRG * j;
         double v = 0.0;
 #pragma unroll
         for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? part[j][t] : 0.0;
@@ -219,15 +225,15 @@ __device__ __forceinline__ double gj_entry(double s, double srp, double spc, dou
 
 // S^{-1} by Gauss-Jordan without pivoting, in registers (the layout of
 // sm_build_s), two pivots per round.  A round publishes the whole of S to one
-// of two LDS copies (every thread stores its 4 entries: no branches) and
+// of two LDS copies (every thread stores its entries: no branches) and
 // takes one barrier.  Every thread then reads rows p, p+1 at its column and
 // columns p, p+1 at its rows, forms row p+1 and column p+1 as step p leaves
 // them and the pivot of step p+1, with exactly the operations the threads
-// that own those entries apply, and takes its 4 entries through both steps:
+// that own those entries apply, and takes its entries through both steps:
 // the result is bit for bit that of one pivot per barrier.  piv[p] receives
 // the pivots, the sequential ratios.  Ends with S^{-1} in Sinv (after a
 // barrier).
-__device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
+__device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[kSmEPT],
                                              double (*Sx)[kSmChunk][kSmChunk], double* piv,
                                              double (*Sinv)[kSmPad])
 {
@@ -237,17 +243,17 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
     for (; p + 1 < kp; p += 2, ++round) {
         double (*S)[kSmChunk] = Sx[round & 1];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) S[gr0 + 8 * j][gc] = sv[j];
+        for (int j = 0; j < kSmEPT; ++j) S[gr0 + kSmRG * j][gc] = sv[j];
         __syncthreads();
         const double d = S[p][p];
         const double rd = 1.0 / d;
         const double s0c = S[p][gc], s1c = S[p + 1][gc];
         const double s0q = S[p][p + 1], s1p = S[p + 1][p], s1q = S[p + 1][p + 1];
-        double c0[4], c1[4];
+        double c0[kSmEPT], c1[kSmEPT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            c0[j] = S[gr0 + 8 * j][p];
-            c1[j] = S[gr0 + 8 * j][p + 1];
+        for (int j = 0; j < kSmEPT; ++j) {
+            c0[j] = S[gr0 + kSmRG * j][p];
+            c1[j] = S[gr0 + kSmRG * j][p + 1];
         }
         // step p: this thread's entries, row p+1 at column gc, column p+1 at
         // its rows, and the next pivot
@@ -257,8 +263,8 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
         const double rd2 = 1.0 / d2;
         const bool colq = gc == p + 1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = gr0 + 8 * j;
+        for (int j = 0; j < kSmEPT; ++j) {
+            const int r = gr0 + kSmRG * j;
             const double e = gj_entry(sv[j], c0[j], s0c, rd, r == p, colp);
             const double w = gj_entry(c1[j], c0[j], s0q, rd, r == p, false);
             // step p + 1
@@ -272,19 +278,19 @@ __device__ __forceinline__ void sm_eliminate(int kp, int tid, double (&sv)[4],
     if (p < kp) {   // an odd last pivot: one step
         double (*S)[kSmChunk] = Sx[round & 1];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) S[gr0 + 8 * j][gc] = sv[j];
+        for (int j = 0; j < kSmEPT; ++j) S[gr0 + kSmRG * j][gc] = sv[j];
         __syncthreads();
         const double d = S[p][p];
         const double rd = 1.0 / d;
         const double s0c = S[p][gc];
         const bool colp = gc == p;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            sv[j] = gj_entry(sv[j], S[gr0 + 8 * j][p], s0c, rd, gr0 + 8 * j == p, colp);
+        for (int j = 0; j < kSmEPT; ++j)
+            sv[j] = gj_entry(sv[j], S[gr0 + kSmRG * j][p], s0c, rd, gr0 + kSmRG * j == p, colp);
         if (tid == 0) piv[p] = d;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Sinv[gr0 + 8 * j][gc] = sv[j];
+    for (int j = 0; j < kSmEPT; ++j) Sinv[gr0 + kSmRG * j][gc] = sv[j];
     __syncthreads();
 }
 
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
     if (tid < kSmChunk) lcolp[tid] = sm_batched_col(a, q, a.chunk - 1, tid < kp ? tid : kp - 1);
     __syncthreads();
     const double* Pp = a.Pp + q * a.ws_mstride;
-    double sv[4];
+    double sv[kSmEPT];
     sm_build_s(Pp, a.n, a.nct, kp, lcolp, tid, sv);
     sm_eliminate(kp, tid, sv, Sx, piv, Sinv);
     double* out = const_cast<double*>(a.sinv) + q * a.ws_mstride;
@@ -351,7 +357,7 @@ template <bool BATCHED, int RB>
 __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
     constexpr int ROWS = 16 * RB;               // rows of B: RB matrix-core row blocks
-    constexpr int VPT = ROWS / 8;               // entries of V - E (and Y) per thread
+    constexpr int VPT = ROWS / kSmRG;           // entries of V - E (and Y) per thread
     __shared__ double Sinv[kSmChunk][kSmPad];   // S^{-1}
     __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
     __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
@@ -461,14 +467,14 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 
     if (kp > 0) {
         // this tile's rows of V - E, the column-tile partials summed in order;
-        // thread t handles rows t/32 + 8k, k < VPT, at column t%32
+        // thread t handles rows t/kSmChunk + kSmRG k, k < VPT, at column t%kSmChunk
         const int vr0 = tid / kSmChunk, vm = tid % kSmChunk;
         double vpart[VPT][kSmMaxTiles];
         {
             const int mq = vm < kp ? vm : kp - 1;
 #pragma unroll
             for (int k = 0; k < VPT; ++k) {
-                const int vi = i0 + vr0 + 8 * k;
+                const int vi = i0 + vr0 + kSmRG * k;
                 const int row = vi < n ? vi : n - 1;
 #pragma unroll
                 for (int t = 0; t < kSmMaxTiles; ++t)
@@ -480,25 +486,25 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
             for (int e = tid; e < kSmChunk * kSmPad; e += kSmThreads) (&Sinv[0][0])[e] = src[e];
         } else {
             __shared__ double Sx[2][kSmChunk][kSmChunk];   // S, double-buffered
-            double sv[4];
+            double sv[kSmEPT];
             sm_build_s(Pp, n, nct, kp, lcolp, tid, sv);
             sm_eliminate(kp, tid, sv, Sx, piv, Sinv);
         }
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
-            const int vi = i0 + vr0 + 8 * k;
+            const int vi = i0 + vr0 + kSmRG * k;
             double v = 0.0;
 #pragma unroll
             for (int t = 0; t < kSmMaxTiles; ++t) v += (t < nct) ? vpart[k][t] : 0.0;
             if (lcolp[vm] == vi && vm < kp) v -= 1.0;
-            Vl[vr0 + 8 * k][vm] = (vi < n && vm < kp) ? v : 0.0;
+            Vl[vr0 + kSmRG * k][vm] = (vi < n && vm < kp) ? v : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             double y = 0.0;
-            for (int p = 0; p < kp; ++p) y = fma(Vl[vr0 + 8 * k][p], Sinv[p][vm], y);
-            Y[vr0 + 8 * k][vm] = (vm < kp) ? y : 0.0;
+            for (int p = 0; p < kp; ++p) y = fma(Vl[vr0 + kSmRG * k][p], Sinv[p][vm], y);
+            Y[vr0 + kSmRG * k][vm] = (vm < kp) ? y : 0.0;
         }
         if constexpr (!BATCHED) {
             if (blockIdx.x == 0 && blockIdx.y == 0 && a.ratio != nullptr && tid < kp) a.ratio[tid] = piv[tid];
@@ -524,10 +530,12 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
             for (int s4 = 0; s4 < kSmChunk / 4; ++s4) yop[rb][s4] = -Y[16 * rb + lr][4 * s4 + g];
         }
     }
-    int urow[2] = {0, 0};       // rows of u for moves lr and 16 + lr
+    int urow[kSmMB];            // rows of u for moves 16 mb + lr
+#pragma unroll
+    for (int mb = 0; mb < kSmMB; ++mb) urow[mb] = 0;
     if (kn > 0) {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
+        for (int mb = 0; mb < kSmMB; ++mb) {
             const int m = 16 * mb + lr;
             urow[mb] = lurow[m < kn ? m : kn - 1];
         }
@@ -539,7 +547,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     struct TileIn {
         v4d b[RB];
         double r[kSmChunk / 4];
-        float u[2][4];
+        float u[kSmMB][4];
     };
     typedef double d2 __attribute__((ext_vector_type(2)));
     typedef float f4 __attribute__((ext_vector_type(4)));
@@ -572,7 +580,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         }
         if (kn > 0) {
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
+            for (int mb = 0; mb < kSmMB; ++mb) {
                 const float* urw = u + (int64_t)urow[mb] * a.u_ld;
                 if (a.vec_u && whole) {
                     const f4 x = *reinterpret_cast<const f4*>(urw + c + cq);
@@ -599,11 +607,11 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         const int c0 = y * a.tl;
         const int cend = min(n, c0 + a.tl);
         const int ntile = (cend - c0 + kSmTile - 1) / kSmTile;
-        v4d vacc[RB][2];
+        v4d vacc[RB][kSmMB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) vacc[rb][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int mb = 0; mb < kSmMB; ++mb) vacc[rb][mb] = v4d{0.0, 0.0, 0.0, 0.0};
         // Wavefront w takes tiles w, w+4, ...: K of them.  Loads run kSmAhead
         // tiles ahead of the tile being computed, through a ring of buffers
         // whose indices are compile-time constants (the loop is unrolled by
@@ -657,7 +665,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
                         for (int r = 0; r < 4; ++r) {
                             const double bval = (c + cq + r < cend) ? acc[r] : 0.0;
 #pragma unroll
-                            for (int mb = 0; mb < 2; ++mb)
+                            for (int mb = 0; mb < kSmMB; ++mb)
                                 vacc[rb][mb] = mfma_f64_16x16x4(bval, (double)cur.u[mb][r], vacc[rb][mb]);
                         }
                     }
@@ -669,7 +677,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
+                for (int mb = 0; mb < kSmMB; ++mb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         Vw[w][16 * rb + 4 * r + g][16 * mb + lr] = vacc[rb][mb][r];
