@@ -262,7 +262,7 @@ BLIP_API int blip_submit(blip_table t, blip_plan plan, const blip_eval_opts* opt
  * holds `rotate` consecutive blocks and timed launch i uses block i mod
  * rotate, so that a launch does not find its rows left in the caches by the
  * previous one; otherwise (rotate must be 1) it tunes blip_eval_batched with
- * capacity npos (P in {8,16,32,64}).  o runs over
+ * capacity npos (P in {4,8,16,32,64}).  o runs over
  * {1,2,4} (FP32 storage) or {2,4,8} (16-bit storage).  Each shape is timed
  * as bursts of max(8, rotate) back-to-back launches (one untimed burst, then
  * five timed), the figure being the median over bursts of the mean time per

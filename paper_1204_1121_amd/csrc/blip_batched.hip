@@ -583,7 +583,7 @@ BLIP_API int blip_autotune(blip_table t, const double* pos, const int64_t* offse
     if (rc != BLIP_OK) return rc;
     if (npos == 0 || (batched && nw == 0)) return fail(BLIP_E_ARG, "nothing to tune (npos == 0)");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<int> Ps = batched ? std::vector<int>{8, 16, 32, 64} : std::vector<int>{1, 2, 4, 8};
+    std::vector<int> Ps = batched ? std::vector<int>{4, 8, 16, 32, 64} : std::vector<int>{1, 2, 4, 8};
     std::vector<int> Os = t->esize == 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{2, 4, 8};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
