@@ -117,3 +117,67 @@ def test_serving_workload_tables():
     finally:
         for t in tables:
             t.free()
+
+
+def test_submit_paths_and_errors(systems):
+    """blip_submit directly: from pageable and from pinned host memory, the
+    direct launch equals blip_eval bit for bit and the event completes; a
+    plan given buffers other than its own, or the wrong number of offsets,
+    is refused before anything is enqueued."""
+    import ctypes
+    from paper_1204_1121_amd import blip
+    specs, coefs, tables = systems
+    t = tables[0]
+    rng = np.random.default_rng(21)
+    pos = rng.uniform(0, 6, (300, 3))
+    L = blip.lib()
+    dev_pos = torch.zeros((512, 3), dtype=torch.float64, device="cuda")
+    out = t.alloc_outputs(512)
+    st = torch.cuda.Stream()
+    ev = torch.cuda.Event()
+    ev.record(st)
+    ref = t.eval(torch.from_numpy(pos).cuda())
+    torch.cuda.synchronize()
+    pinned = torch.from_numpy(pos).pin_memory()
+    for label, host in (("pageable", np.ascontiguousarray(pos)), ("pinned", pinned)):
+        say(f"blip_submit from {label} host memory")
+        for x in out:
+            x.zero_()
+        torch.cuda.synchronize()          # the zeros land before the submit's stream runs
+        hp = host.ctypes.data if isinstance(host, np.ndarray) else host.data_ptr()
+        rc = L.blip_submit(t.handle, None, None, ctypes.c_void_p(hp), 300,
+                           ctypes.c_void_p(dev_pos.data_ptr()), None, 0, None,
+                           *[ctypes.c_void_p(x.data_ptr()) for x in out],
+                           ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(ev.cuda_event))
+        assert rc == 0, L.blip_last_error()
+        ev.synchronize()
+        assert ev.query()
+        for k, a, b in zip(("val", "grad", "lap"), out, ref):
+            np.testing.assert_array_equal(to_np(a[:300]), to_np(b), err_msg=f"{label} {k}")
+    say("blip_submit argument errors")
+    off = torch.zeros(5, dtype=torch.int64, device="cuda")
+    ws = t.workspace(512)
+    plan = t.plan(dev_pos, off, out, ws, capacity=512)
+    other = torch.zeros((512, 3), dtype=torch.float64, device="cuda")
+    hoff = np.array([0, 100, 200, 300, 300], dtype=np.int64)
+    hp = pinned.data_ptr()
+    rc = L.blip_submit(t.handle, plan._h, None, ctypes.c_void_p(hp), 300,
+                       ctypes.c_void_p(other.data_ptr()), ctypes.c_void_p(hoff.ctypes.data), 5,
+                       ctypes.c_void_p(off.data_ptr()), None, None, None,
+                       ctypes.c_void_p(st.cuda_stream), None)
+    assert rc == -1 and b"captured buffers" in L.blip_last_error()
+    rc = L.blip_submit(t.handle, plan._h, None, ctypes.c_void_p(hp), 300,
+                       ctypes.c_void_p(dev_pos.data_ptr()), ctypes.c_void_p(hoff.ctypes.data), 4,
+                       ctypes.c_void_p(off.data_ptr()), None, None, None,
+                       ctypes.c_void_p(st.cuda_stream), None)
+    assert rc == -1 and b"offsets" in L.blip_last_error()
+    say("blip_submit through the plan")
+    rc = L.blip_submit(t.handle, plan._h, None, ctypes.c_void_p(hp), 300,
+                       ctypes.c_void_p(dev_pos.data_ptr()), ctypes.c_void_p(hoff.ctypes.data), 5,
+                       ctypes.c_void_p(off.data_ptr()), None, None, None,
+                       ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(ev.cuda_event))
+    assert rc == 0, L.blip_last_error()
+    ev.synchronize()
+    for k, a, b in zip(("val", "grad", "lap"), out, ref):
+        np.testing.assert_array_equal(to_np(a[:300]), to_np(b), err_msg=f"plan {k}")
+    plan.free()
