@@ -252,3 +252,47 @@ def test_ratio_values_batched(blip, o):
     check_ratio({"ratio": to_np(r[:total]), "grad": to_np(g[:total]), "lap": to_np(lr[:total])},
                 ref, vals, allinv_np, allrows, 1e-5, "batched values vs oracle")
     t.free()
+
+
+def test_ratio_at_the_orbital_limit(blip):
+    """The largest table the ratio epilogue takes in FP32 (4,096 orbitals: 16
+    chunks of 64 lanes x 4 elements, 16 KB rows), against the oracle and the
+    FP64 dot of blip_eval's own orbitals; one orbital more is refused."""
+    rng = np.random.default_rng(41)
+    A = np.diag([4.0, 4.5, 5.0])
+    n = (8, 8, 8)
+    L = 4096
+    c = rng.uniform(-1, 1, n + (L,)).astype(np.float32)
+    t = blip.Table(A, n, c, "f32")
+    try:
+        npos = 24
+        moves = rng.uniform(-2, 7, (npos, 3))
+        inv_rows = rng.normal(0, 1, (npos, L))
+        say(f"ratio at L={L}")
+        p = torch.from_numpy(moves).cuda()
+        inv = torch.from_numpy(inv_rows).cuda()
+        r, g, l = t.ratio(p, inv)
+        v, gg, ll = t.eval(p)
+        torch.cuda.synchronize()
+        got = {"ratio": to_np(r), "grad": to_np(g), "lap": to_np(l)}
+        vals = oracle.evaluate(A, n, c, moves, nthreads=8)
+        ref = oracle.ratio(A, n, c, moves, inv_rows, np.arange(npos), nthreads=8)
+        check_ratio(got, ref, vals, inv_rows, np.arange(npos), 1e-5, "vs oracle")
+        mine = {"ratio": np.einsum("jl,jl->j", to_np(v).astype(np.float64), inv_rows),
+                "grad": np.einsum("jcl,jl->jc", to_np(gg).astype(np.float64), inv_rows),
+                "lap": np.einsum("jl,jl->j", to_np(ll).astype(np.float64), inv_rows)}
+        check_ratio(got, mine, vals, inv_rows, np.arange(npos), 1e-13, "vs dot of blip_eval")
+        for k, a in (("val", v), ("grad", gg), ("lap", ll)):
+            err = np.max(np.abs(to_np(a) - vals[k])) / np.max(np.abs(vals[k]))
+            say(f"  blip_eval {k} at L={L}: {err:.2e}")
+            assert err <= 1e-5
+    finally:
+        t.free()
+    c2 = rng.uniform(-1, 1, n + (L + 1,)).astype(np.float32)
+    t2 = blip.Table(A, n, c2, "f32")
+    try:
+        inv2 = torch.zeros((4, L + 1), dtype=torch.float64, device="cuda")
+        with pytest.raises(blip.BlipError, match="too large"):
+            t2.ratio(torch.zeros((4, 3), dtype=torch.float64, device="cuda"), inv2)
+    finally:
+        t2.free()
