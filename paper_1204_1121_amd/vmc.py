@@ -85,14 +85,18 @@ class Walkers:
             # the ratio pass's launch shape measured for this table and step
             # size, if the package's tuning cache holds one (else the default)
             TuneCache().apply(table, npos, batched=True, ratio=True)
-        if inv_t is None:
-            self.t.eval(self.pos.view(npos, 3), grad=False, out=(self.val, None, None),
-                        stream=stream)
-            D = self.val.view(2 * W, n, n).double()
-            inv_t = torch.linalg.inv(D).transpose(1, 2)
-        if tuple(inv_t.shape) != (W, 2, n, n) and tuple(inv_t.shape) != (2 * W, n, n):
-            raise ValueError(f"inv_t must be [W, 2, n, n] (got {tuple(inv_t.shape)})")
-        self.inv = inv_t.reshape(2 * W, n, n).to(torch.float64).contiguous()
+        # the first inverses are set up on the walkers' stream (after the
+        # evaluation that fills their Slater matrices), where every later
+        # kernel reads them
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            if inv_t is None:
+                self.t.eval(self.pos.view(npos, 3), grad=False, out=(self.val, None, None),
+                            stream=stream)
+                D = self.val.view(2 * W, n, n).double()
+                inv_t = torch.linalg.inv(D).transpose(1, 2)
+            if tuple(inv_t.shape) != (W, 2, n, n) and tuple(inv_t.shape) != (2 * W, n, n):
+                raise ValueError(f"inv_t must be [W, 2, n, n] (got {tuple(inv_t.shape)})")
+            self.inv = inv_t.reshape(2 * W, n, n).to(torch.float64).contiguous()
 
     def _call(self, rc):
         _b.check(rc)
@@ -177,13 +181,17 @@ class Walkers:
         holds the earlier decisions (one masked step per electron; for
         comparisons on small systems, not a fast path)."""
         W, n = self.W, self.n
-        inf = torch.full_like(uniform, float("inf"))
-        zero = torch.zeros_like(eta)
-        for g in range(2 * n):
-            e_g = zero.clone()
-            e_g[:, g] = eta[:, g]
-            u_g = inf.clone()
-            u_g[:, g] = uniform[:, g]
-            j = g % n
-            self.step(e_g, u_g, energy=False, j0=j, j1=j + 1)
+        # the masked random numbers are written on the walkers' stream, in
+        # order with the steps that read them
+        with torch.cuda.stream(self.stream if self.stream is not None
+                               else torch.cuda.current_stream()):
+            inf = torch.full_like(uniform, float("inf"))
+            zero = torch.zeros_like(eta)
+            for g in range(2 * n):
+                e_g = zero.clone()
+                e_g[:, g] = eta[:, g]
+                u_g = inf.clone()
+                u_g[:, g] = uniform[:, g]
+                j = g % n
+                self.step(e_g, u_g, energy=False, j0=j, j1=j + 1)
         return self.kinetic() if energy else None

@@ -200,3 +200,39 @@ def test_sorted_ratio_pass_same_chain(setup):
                                    atol=1e-12 * float(np.abs(to_np(eb)).max()))
         say(f"  step {step}: accepted {int(to_np(ca).sum())} of {nw * 2 * n}")
     t.free()
+
+
+def test_walkers_on_side_streams(setup):
+    """Walkers stepped on their own (non-default) streams: the first inverses
+    set up from scratch, quasi-simultaneous steps and a particle-by-particle
+    sweep give bit for bit what the same walkers give on the default stream,
+    with two walker sets stepping concurrently on two streams."""
+    blip, vmc, t, coef, pos, inv, rng = setup
+    p0 = torch.from_numpy(pos.copy()).cuda()
+    ref = vmc.Walkers(t, p0.clone())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = vmc.Walkers(t, p0.clone(), stream=s1)
+    b = vmc.Walkers(t, p0.clone(), stream=s2)
+    torch.cuda.synchronize()
+    say("walkers on side streams: setup inverses")
+    assert torch.equal(ref.inv, a.inv) and torch.equal(ref.inv, b.inv)
+    for step in range(3):
+        eta = torch.from_numpy(rng.normal(0, 0.3, (W, 2 * L, 3))).cuda()
+        uni = torch.from_numpy(rng.uniform(0, 1, (W, 2 * L))).cuda()
+        torch.cuda.synchronize()
+        cr, er = ref.step(eta, uni)
+        ca, ea = a.step(eta, uni)
+        cb, eb = b.step(eta, uni)
+        torch.cuda.synchronize()
+        for w in (a, b):
+            assert torch.equal(w.pos, ref.pos) and torch.equal(w.inv, ref.inv), step
+        assert torch.equal(ea, er) and torch.equal(eb, er), step
+    eta = torch.from_numpy(rng.normal(0, 0.3, (W, 2 * L, 3))).cuda()
+    uni = torch.from_numpy(rng.uniform(0, 1, (W, 2 * L))).cuda()
+    torch.cuda.synchronize()
+    say("walkers on side streams: particle-by-particle sweep")
+    er = ref.pbp_sweep(eta, uni)
+    ea = a.pbp_sweep(eta, uni)
+    torch.cuda.synchronize()
+    assert torch.equal(a.pos, ref.pos) and torch.equal(a.inv, ref.inv)
+    assert torch.equal(ea, er)
