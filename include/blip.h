@@ -426,7 +426,10 @@ BLIP_API int blip_eval_ratio_values_batched(blip_table t, const double* pos,
  * zero yields non-finite rows exactly as the rank-1 form would.
  * Asynchronous on the stream, no allocation; ceil(k/32)+1 launches (about
  * one more per repeated electron).  k = 0 enqueues nothing.  BLIP_E_ARG for
- * a size or index out of range, BLIP_E_ALIGN for misaligned pointers.
+ * a size or index out of range, or when inv or u spans 2 GiB or more (the
+ * kernels address a matrix with 31-bit byte offsets; at n <= 4096 only a
+ * leading dimension far above n gets there), BLIP_E_ALIGN for misaligned
+ * pointers.
  */
 BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float* u,
                             int64_t u_nrows, int64_t u_ld, const int64_t* cols,
@@ -464,7 +467,8 @@ BLIP_API size_t blip_sm_workspace_size(int64_t n);
  * of blip_sm_update on the same list, so the results are bitwise equal.
  * Everything is read on the device and the launch sequence depends only on
  * nmat, n and max_k: a step can be captured in a graph.  Asynchronous, no
- * allocation.  BLIP_E_ARG / BLIP_E_ALIGN on host-checkable errors.
+ * allocation.  BLIP_E_ARG / BLIP_E_ALIGN on host-checkable errors (as for
+ * blip_sm_update, one matrix of inv or u must span less than 2 GiB).
  */
 BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t inv_mstride,
                                     int64_t inv_ld, const float* u, int64_t u_mstride,

@@ -92,8 +92,8 @@ struct SmArgs {
     int64_t ratio_ld;        // ratios of matrix q start at ratio + q * ratio_ld
     const double* sinv;      // [nmat] S^{-1} of the applied chunk, from sm_sinv_kernel
     int* act;                // [1 + nmat] matrices with moves in the launch, from it
-    int vec_b;               // 1: rows of B (every matrix) start 16-byte aligned
-    int vec_u;               // 1: rows of u (every matrix) start 16-byte aligned
+    uint32_t inv_bytes;      // bytes of B (of one matrix) the tile loads may touch
+    uint32_t u_bytes;        // bytes of u (of one matrix) the tile loads may touch
 };
 
 // Column tiles: at most kSmMaxTiles per row (so summing V's partials stays
@@ -347,13 +347,13 @@ __global__ __launch_bounds__(kSmThreads) void sm_sinv_kernel(SmArgs a)
 // tiles w, w+4, ... of a column tile, and the four partial V tiles are added
 // in wavefront order.
 //
-// Loads are written without data-dependent branches: addresses are clamped
-// into bounds and unwanted values replaced by zero, so each group of loads is
-// issued back to back.  Wide accesses are used for whole tiles when the host
-// has found the rows 16-byte aligned; a ragged last tile takes the clamped
-// scalar path, which reads the same values.  Only the uniform tests kp > 0
-// and kn > 0 guard buffers that may be absent.
-template <bool BATCHED, int RB>
+// The tile loads are buffer loads, which read zero past a buffer's extent:
+// every tile, the ragged last one included, issues the same loads with no
+// bounds test, and values past the tile's last column are masked where they
+// are used.  The kernels come in two forms, with 16-byte loads when the host
+// has found the rows of B and u 16-byte aligned and 8- and 4-byte loads
+// otherwise; both read the same values.
+template <bool BATCHED, int RB, bool VEC>
 __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 {
     constexpr int ROWS = 16 * RB;               // rows of B: RB matrix-core row blocks
@@ -516,7 +516,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // g = l/16 selects the columns c + 4g .. c + 4g + 3 of a tile and the
     // moves 4s + g.
     const int lane = tid & 63;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront: uniform
     const int lr = lane & 15, g = lane >> 4;
     int irow[RB], sl[RB];
     double yop[RB][kSmChunk / 4];   // (-Y)^T operands: -Y[row][4s + g]
@@ -552,49 +552,66 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     typedef double d2 __attribute__((ext_vector_type(2)));
     typedef float f4 __attribute__((ext_vector_type(4)));
     const int cq = 4 * g;   // first of the lane's columns within a tile
-    auto load_tile = [&](int c, int cend, TileIn& in) {
-        const bool whole = c + kSmTile <= cend;   // uniform per wavefront
+    // Tile loads go through buffer resources over B, R and u.  A load past a
+    // resource's extent returns zero without touching memory, so no load
+    // needs a bounds test or a clamp: every tile issues the same loads, and
+    // the wait for a tile leaves the loads of the next one in flight.
+    // Entries past a tile's last column are loaded and never used.  An
+    // absent R or u (no moves applied or prepared) is an empty resource, and
+    // so are all three for a step with no tile left to fetch: its loads cost
+    // no memory traffic.
+    const int bytes_b = (int)a.inv_bytes;
+    const int bytes_r = kp > 0 ? kp * n * (int)sizeof(double) : 0;
+    const int bytes_u = kn > 0 ? (int)a.u_bytes : 0;
+    int boff[RB], uoff[kSmMB];   // byte offsets of the lane's rows
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) boff[rb] = (int)(irow[rb] * a.ld * (int64_t)sizeof(double));
+#pragma unroll
+    for (int mb = 0; mb < kSmMB; ++mb) uoff[mb] = (int)(urow[mb] * a.u_ld * (int64_t)sizeof(float));
+    // moved row 4 s4 + g at the column of slot lr (rows past kp read zero)
+    const int roff = ((4 * (lr & 3) + (lr >> 2)) + g * n) * (int)sizeof(double);
+    auto load_tile = [&](int c, bool live, TileIn& in) {   // live: uniform
+        const __amdgpu_buffer_rsrc_t rs_b =
+            __builtin_amdgcn_make_buffer_rsrc(inv, 0, live ? bytes_b : 0, kBufWord3);
+        const __amdgpu_buffer_rsrc_t rs_r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double*>(Rp), 0, live ? bytes_r : 0, kBufWord3);
+        const __amdgpu_buffer_rsrc_t rs_u = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(u), 0, live ? bytes_u : 0, kBufWord3);
+        const int c8 = c * (int)sizeof(double);
+        const int c4 = c * (int)sizeof(float);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const double* brow = inv + (int64_t)irow[rb] * a.ld;
-            if (a.vec_b && whole) {
-                const d2 x0 = *reinterpret_cast<const d2*>(brow + c + cq);
-                const d2 x1 = *reinterpret_cast<const d2*>(brow + c + cq + 2);
+            const int o = boff[rb] + c8 + cq * (int)sizeof(double);
+            if constexpr (VEC) {
+                const d2 x0 = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs_b, o, 0, 0));
+                const d2 x1 = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs_b, o + 16, 0, 0));
                 in.b[rb] = v4d{x0.x, x0.y, x1.x, x1.y};
             } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int col = c + cq + r;
-                    in.b[rb][r] = brow[col < cend ? col : cend - 1];
-                }
+                for (int r = 0; r < 4; ++r)
+                    in.b[rb][r] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs_b, o + 8 * r, 0, 0));
             }
         }
-        if (kp > 0) {
-            const int cs = c + 4 * (lr & 3) + (lr >> 2);   // column of slot lr
-            const int col = cs < cend ? cs : cend - 1;
 #pragma unroll
-            for (int s4 = 0; s4 < kSmChunk / 4; ++s4) {
-                const int m = 4 * s4 + g;
-                in.r[s4] = Rp[(int64_t)(m < kp ? m : kp - 1) * n + col];
-            }
-        }
-        if (kn > 0) {
+        for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+            in.r[s4] = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(
+                            rs_r, roff + 4 * s4 * n * (int)sizeof(double) + c8, 0, 0));
 #pragma unroll
-            for (int mb = 0; mb < kSmMB; ++mb) {
-                const float* urw = u + (int64_t)urow[mb] * a.u_ld;
-                if (a.vec_u && whole) {
-                    const f4 x = *reinterpret_cast<const f4*>(urw + c + cq);
-                    in.u[mb][0] = x.x;
-                    in.u[mb][1] = x.y;
-                    in.u[mb][2] = x.z;
-                    in.u[mb][3] = x.w;
-                } else {
+        for (int mb = 0; mb < kSmMB; ++mb) {
+            const int o = uoff[mb] + c4 + cq * (int)sizeof(float);
+            if constexpr (VEC) {
+                const f4 x = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs_u, o, 0, 0));
+                in.u[mb][0] = x.x;
+                in.u[mb][1] = x.y;
+                in.u[mb][2] = x.z;
+                in.u[mb][3] = x.w;
+            } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int col = c + cq + r;
-                        in.u[mb][r] = urw[col < cend ? col : cend - 1];
-                    }
-                }
+                for (int r = 0; r < 4; ++r)
+                    in.u[mb][r] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(rs_u, o + 4 * r, 0, 0));
             }
         }
     };
@@ -616,57 +633,64 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         // tiles ahead of the tile being computed, through a ring of buffers
         // whose indices are compile-time constants (the loop is unrolled by
         // the ring length); the next loads go out before this tile's stores,
-        // so waiting for a tile never waits for stores.
+        // so waiting for a tile never waits for stores.  Every step issues
+        // its loads, past the last tile too (as empty loads): with the same
+        // loads in flight on every path, the wait for a tile leaves the next
+        // tile's loads outstanding.
         const int K = w < ntile ? (ntile - w + kSmWaves - 1) / kSmWaves : 0;
+        auto tile_col = [&](int k) { return c0 + (w + kSmWaves * k) * kSmTile; };
         TileIn buf[kSmAhead + 1];
+        if (K > 0) {
 #pragma unroll
-        for (int j = 0; j < kSmAhead; ++j)
-            if (j < K) load_tile(c0 + (w + kSmWaves * j) * kSmTile, cend, buf[j]);
-        for (int kb = 0; kb < K; kb += kSmAhead + 1) {
+            for (int j = 0; j < kSmAhead; ++j) load_tile(tile_col(j), j < K, buf[j]);
+            for (int kb = 0; kb < K; kb += kSmAhead + 1) {
 #pragma unroll
-            for (int j = 0; j <= kSmAhead; ++j) {
-                const int k = kb + j;
-                if (k >= K) break;   // uniform per wavefront
-                if (k + kSmAhead < K)
-                    load_tile(c0 + (w + kSmWaves * (k + kSmAhead)) * kSmTile, cend,
+                for (int j = 0; j <= kSmAhead; ++j) {
+                    const int k = kb + j;
+                    if (k >= K) break;   // uniform per wavefront
+                    load_tile(tile_col(k + kSmAhead), k + kSmAhead < K,
                               buf[(j + kSmAhead) % (kSmAhead + 1)]);
-                const TileIn& cur = buf[j];
-                const int c = c0 + (w + kSmWaves * k) * kSmTile;
+                    const TileIn& cur = buf[j];
+                    const int c = c0 + (w + kSmWaves * k) * kSmTile;
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    v4d acc = cur.b[rb];
-                    // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
-                    if (kp > 0) {
+                    for (int rb = 0; rb < RB; ++rb) {
+                        v4d acc = cur.b[rb];
+                        // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
+                        if (kp > 0) {
 #pragma unroll
-                        for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
-                            acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
-                    }
-                    const int i = i0 + 16 * rb + lr;
-                    if (kp > 0 && i < n) {
-                        double* brow = inv + (int64_t)i * a.ld;
-                        if (a.vec_b && c + kSmTile <= cend) {
-                            *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
-                            *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
-                        } else {
+                            for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+                                acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
+                        }
+                        const int i = i0 + 16 * rb + lr;
+                        if (kp > 0 && i < n) {
+                            double* brow = inv + (int64_t)i * a.ld;
+                            if (VEC && c + kSmTile <= cend) {
+                                *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
+                                *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                            }
+                        }
+                        if (sl[rb] >= 0) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                                if (c + cq + r < cend) Rn[(int64_t)sl[rb] * n + c + cq + r] = acc[r];
                         }
-                    }
-                    if (sl[rb] >= 0) {
+                        // V += B' U^T, k-step r over the columns c + 4q + r
+                        // (columns past the tile contribute zero: both operands are
+                        // replaced, so that what was loaded there cannot reach V)
+                        if (kn > 0) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (c + cq + r < cend) Rn[(int64_t)sl[rb] * n + c + cq + r] = acc[r];
-                    }
-                    // V += B' U^T, k-step r over the columns c + 4q + r
-                    // (columns past the tile contribute zero)
-                    if (kn > 0) {
+                            for (int r = 0; r < 4; ++r) {
+                                const bool in = c + cq + r < cend;
+                                const double bval = in ? acc[r] : 0.0;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const double bval = (c + cq + r < cend) ? acc[r] : 0.0;
-#pragma unroll
-                            for (int mb = 0; mb < kSmMB; ++mb)
-                                vacc[rb][mb] = mfma_f64_16x16x4(bval, (double)cur.u[mb][r], vacc[rb][mb]);
+                                for (int mb = 0; mb < kSmMB; ++mb)
+                                    vacc[rb][mb] = mfma_f64_16x16x4(
+                                        bval, (double)(in ? cur.u[mb][r] : 0.0f), vacc[rb][mb]);
+                            }
                         }
                     }
                 }
@@ -704,24 +728,38 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
 // SIMD); asked for two wavefronts it fits 238 without spilling, and the
 // second hides load latency (44.6 against 55.5 us per matrix-step on the
 // batched update of 64 matrices).
+template <bool VEC>
 __global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void sm_chunk_kernel(SmArgs a)
 {
-    sm_chunk_body<false, 1>(a);
+    sm_chunk_body<false, 1, VEC>(a);
 }
 
-template <int RB>
+template <int RB, bool VEC>
 __global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void sm_chunk_batched_kernel(SmArgs a)
 {
-    sm_chunk_body<true, RB>(a);
+    sm_chunk_body<true, RB, VEC>(a);
 }
 
-hipError_t sm_launch(const SmArgs& a, hipStream_t s)
+hipError_t sm_launch(const SmArgs& a, bool vec, hipStream_t s)
 {
     const dim3 grid((unsigned)((a.n + 15) / 16), (unsigned)a.nct);
-    hipLaunchKernelGGL(sm_chunk_kernel, grid, dim3(kSmThreads), 0, s, a);
+    if (vec)
+        hipLaunchKernelGGL(sm_chunk_kernel<true>, grid, dim3(kSmThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(sm_chunk_kernel<false>, grid, dim3(kSmThreads), 0, s, a);
     return hipGetLastError();
+}
+
+// Bytes of a row-major matrix of `rows` rows of n used entries, leading
+// dimension ld, as the tile loads address it: rounded up to 16 bytes, which
+// stays inside the 16-byte block of the last entry.  0 when byte offsets
+// that far (and a tile's reach past them) would not fit in 31 bits.
+uint32_t sm_extent(int64_t rows, int64_t n, int64_t ld, int64_t elem)
+{
+    const int64_t bytes = (((rows - 1) * ld + n) * elem + 15) / 16 * 16;
+    return bytes + 2 * kSmTile * 8 < ((int64_t)1 << 31) ? (uint32_t)bytes : 0;
 }
 
 bool aligned(const void* p, uintptr_t b) { return (reinterpret_cast<uintptr_t>(p) & (b - 1)) == 0; }
@@ -770,6 +808,13 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
         return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
     if (k > 0 && !aligned(workspace, 8)) return fail(BLIP_E_ALIGN, "workspace needs 8-byte alignment");
     if (k == 0) return BLIP_OK;
+    const uint32_t inv_bytes = sm_extent(n, n, inv_ld, sizeof(double));
+    const uint32_t u_bytes = sm_extent(u_nrows, n, u_ld, sizeof(float));
+    if (inv_bytes == 0 || u_bytes == 0)
+        return fail(BLIP_E_ARG, "inv (n = %lld, inv_ld = %lld) or u (%lld rows, u_ld = %lld) "
+                    "spans 2 GiB or more", (long long)n, (long long)inv_ld, (long long)u_nrows,
+                    (long long)u_ld);
+    const bool vec = aligned(inv, 16) && inv_ld % 2 == 0 && aligned(u, 16) && u_ld % 4 == 0;
 
     // Chunks of consecutive moves: at most kSmChunk, and a new chunk whenever
     // an electron would appear twice (the block form replaces distinct rows).
@@ -801,8 +846,8 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
         a.ld = inv_ld;
         a.u = u;
         a.u_ld = u_ld;
-        a.vec_b = aligned(inv, 16) && inv_ld % 2 == 0;
-        a.vec_u = u != nullptr && aligned(u, 16) && u_ld % 4 == 0;
+        a.inv_bytes = inv_bytes;
+        a.u_bytes = u_bytes;
         if (c > 0) {
             const size_t q = c - 1;
             a.kp = (int)len[q];
@@ -820,7 +865,7 @@ BLIP_API int blip_sm_update(int64_t n, double* inv, int64_t inv_ld, const float*
             a.Pn = V[c & 1];
             a.Rn = R[c & 1];
         }
-        hipError_t e = sm_launch(a, s);
+        hipError_t e = sm_launch(a, vec, s);
         if (e != hipSuccess) return fail_hip(e, "sm_chunk_kernel launch");
     }
     return BLIP_OK;
@@ -854,6 +899,11 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         return fail(BLIP_E_ARG, "inv_ld and u_ld must be >= n, acc_ld and ratio_ld >= max_k");
     if (nmat > 1 && (inv_mstride < (n - 1) * inv_ld + n || u_mstride < (n - 1) * u_ld + n))
         return fail(BLIP_E_ARG, "matrix strides smaller than one matrix");
+    const uint32_t inv_bytes = sm_extent(n, n, inv_ld, sizeof(double));
+    const uint32_t u_bytes = sm_extent(n, n, u_ld, sizeof(float));
+    if (inv_bytes == 0 || u_bytes == 0)
+        return fail(BLIP_E_ARG, "one matrix of inv (inv_ld = %lld) or of u (u_ld = %lld) spans "
+                    "2 GiB or more", (long long)inv_ld, (long long)u_ld);
     if (!aligned(inv, 8) || !aligned(u, 4) || !aligned(acc_cols, 4) || !aligned(acc_count, 4) ||
         (ratios && !aligned(ratios, 8)) || !aligned(workspace, 8))
         return fail(BLIP_E_ALIGN, "inv, ratios and workspace need 8-byte, u and lists 4-byte "
@@ -891,8 +941,10 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     a.acc_count = acc_count;
     a.inv_mstride = inv_mstride;
     a.u_mstride = u_mstride;
-    a.vec_b = aligned(inv, 16) && inv_ld % 2 == 0 && inv_mstride % 2 == 0;
-    a.vec_u = u != nullptr && aligned(u, 16) && u_ld % 4 == 0 && u_mstride % 4 == 0;
+    a.inv_bytes = inv_bytes;
+    a.u_bytes = u_bytes;
+    const bool vec = aligned(inv, 16) && inv_ld % 2 == 0 && inv_mstride % 2 == 0 &&
+                     aligned(u, 16) && u_ld % 4 == 0 && u_mstride % 4 == 0;
     a.ws_mstride = ws_m;
     a.ratio_ld = ratio_ld;
     a.sinv = S;
@@ -911,10 +963,14 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         }
         a.Pn = V[c & 1];
         a.Rn = R[c & 1];
-        if (rb == 2)
-            hipLaunchKernelGGL(sm_chunk_batched_kernel<2>, grid, dim3(kSmThreads), 0, s, a);
+        if (rb == 2 && vec)
+            hipLaunchKernelGGL((sm_chunk_batched_kernel<2, true>), grid, dim3(kSmThreads), 0, s, a);
+        else if (rb == 2)
+            hipLaunchKernelGGL((sm_chunk_batched_kernel<2, false>), grid, dim3(kSmThreads), 0, s, a);
+        else if (vec)
+            hipLaunchKernelGGL((sm_chunk_batched_kernel<1, true>), grid, dim3(kSmThreads), 0, s, a);
         else
-            hipLaunchKernelGGL(sm_chunk_batched_kernel<1>, grid, dim3(kSmThreads), 0, s, a);
+            hipLaunchKernelGGL((sm_chunk_batched_kernel<1, false>), grid, dim3(kSmThreads), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail_hip(e, "sm_chunk_batched_kernel launch");
     }

@@ -141,6 +141,10 @@ def test_sm_update_argument_errors(blip):
     assert call(c=okp, ratios=ctypes.c_void_p(0x10004)) == -5
     assert call(c=okp, w=ctypes.c_void_p(0x10004)) == -5
     assert call(c=None, k=0, w=None, wb=0) == 0          # k = 0: nothing to do
+    # a matrix spanning 2 GiB or more (byte offsets past 31 bits) is refused
+    big = (1 << 31) // (8 * (n - 1)) + 1
+    assert call(c=okp, ld=big) == -1 and "2 GiB" in L.blip_last_error().decode()
+    assert call(c=okp, u_ld=2 * big) == -1 and "2 GiB" in L.blip_last_error().decode()
 
 
 def test_sm_update_batched_argument_errors(blip):
@@ -173,6 +177,9 @@ def test_sm_update_batched_argument_errors(blip):
     assert call(w=ctypes.c_void_p(0x10004)) == -5
     assert call(nmat=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
     assert call(max_k=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
+    big = (1 << 31) // (8 * (n - 1)) + 1
+    assert call(nmat=1, ild=big) == -1 and "2 GiB" in L.blip_last_error().decode()
+    assert call(nmat=1, uld=2 * big) == -1 and "2 GiB" in L.blip_last_error().decode()
 
 
 def test_qs_helpers_argument_errors(blip):
