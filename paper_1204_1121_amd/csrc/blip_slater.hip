@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 #include "blip.h"
@@ -570,7 +571,9 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     for (int mb = 0; mb < kSmMB; ++mb) uoff[mb] = (int)(urow[mb] * a.u_ld * (int64_t)sizeof(float));
     // moved row 4 s4 + g at the column of slot lr (rows past kp read zero)
     const int roff = ((4 * (lr & 3) + (lr >> 2)) + g * n) * (int)sizeof(double);
-    auto load_tile = [&](int c, bool live, TileIn& in) {   // live: uniform
+    // HR, HU: std::bool_constant, whether R and u are present (kp > 0,
+    // kn > 0); live: uniform.
+    auto load_tile = [&](auto HR, auto HU, int c, bool live, TileIn& in) {
         const __amdgpu_buffer_rsrc_t rs_b =
             __builtin_amdgcn_make_buffer_rsrc(inv, 0, live ? bytes_b : 0, kBufWord3);
         const __amdgpu_buffer_rsrc_t rs_r = __builtin_amdgcn_make_buffer_rsrc(
@@ -593,11 +596,14 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
                         double, __builtin_amdgcn_raw_buffer_load_b64(rs_b, o + 8 * r, 0, 0));
             }
         }
+        if constexpr (decltype(HR)::value) {
 #pragma unroll
-        for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
-            in.r[s4] = __builtin_bit_cast(
-                double, __builtin_amdgcn_raw_buffer_load_b64(
-                            rs_r, roff + 4 * s4 * n * (int)sizeof(double) + c8, 0, 0));
+            for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+                in.r[s4] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(
+                                rs_r, roff + 4 * s4 * n * (int)sizeof(double) + c8, 0, 0));
+        }
+        if constexpr (!decltype(HU)::value) return;
 #pragma unroll
         for (int mb = 0; mb < kSmMB; ++mb) {
             const int o = uoff[mb] + c4 + cq * (int)sizeof(float);
@@ -619,104 +625,114 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // The batched form walks the column tiles [y0, y1) of its rows (all of
     // them, or one at the ragged end of a batch); the single form takes the
     // column tile blockIdx.y.  V partials are kept per column tile either
-    // way, in the same order.
-    for (int y = y0; y < y1; ++y) {
-        const int c0 = y * a.tl;
-        const int cend = min(n, c0 + a.tl);
-        const int ntile = (cend - c0 + kSmTile - 1) / kSmTile;
-        v4d vacc[RB][kSmMB];
+    // way, in the same order.  The walk is compiled for the three kinds of
+    // launch (R and u both present, or only one of them), so that each
+    // issues only the loads it uses, and the same loads on every path.
+    auto walk = [&](auto HR, auto HU) {
+        for (int y = y0; y < y1; ++y) {
+            const int c0 = y * a.tl;
+            const int cend = min(n, c0 + a.tl);
+            const int ntile = (cend - c0 + kSmTile - 1) / kSmTile;
+            v4d vacc[RB][kSmMB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int mb = 0; mb < kSmMB; ++mb) vacc[rb][mb] = v4d{0.0, 0.0, 0.0, 0.0};
-        // Wavefront w takes tiles w, w+4, ...: K of them.  Loads run kSmAhead
-        // tiles ahead of the tile being computed, through a ring of buffers
-        // whose indices are compile-time constants (the loop is unrolled by
-        // the ring length); the next loads go out before this tile's stores,
-        // so waiting for a tile never waits for stores.  Every step issues
-        // its loads, past the last tile too (as empty loads): with the same
-        // loads in flight on every path, the wait for a tile leaves the next
-        // tile's loads outstanding.
-        const int K = w < ntile ? (ntile - w + kSmWaves - 1) / kSmWaves : 0;
-        auto tile_col = [&](int k) { return c0 + (w + kSmWaves * k) * kSmTile; };
-        TileIn buf[kSmAhead + 1];
-        if (K > 0) {
+                for (int mb = 0; mb < kSmMB; ++mb) vacc[rb][mb] = v4d{0.0, 0.0, 0.0, 0.0};
+            // Wavefront w takes tiles w, w+4, ...: K of them.  Loads run kSmAhead
+            // tiles ahead of the tile being computed, through a ring of buffers
+            // whose indices are compile-time constants (the loop is unrolled by
+            // the ring length); the next loads go out before this tile's stores,
+            // so waiting for a tile never waits for stores.  Every step issues
+            // its loads, past the last tile too (as empty loads): with the same
+            // loads in flight on every path, the wait for a tile leaves the next
+            // tile's loads outstanding.
+            const int K = w < ntile ? (ntile - w + kSmWaves - 1) / kSmWaves : 0;
+            auto tile_col = [&](int k) { return c0 + (w + kSmWaves * k) * kSmTile; };
+            TileIn buf[kSmAhead + 1];
+            if (K > 0) {
 #pragma unroll
-            for (int j = 0; j < kSmAhead; ++j) load_tile(tile_col(j), j < K, buf[j]);
-            for (int kb = 0; kb < K; kb += kSmAhead + 1) {
+                for (int j = 0; j < kSmAhead; ++j) load_tile(HR, HU, tile_col(j), j < K, buf[j]);
+                for (int kb = 0; kb < K; kb += kSmAhead + 1) {
 #pragma unroll
-                for (int j = 0; j <= kSmAhead; ++j) {
-                    const int k = kb + j;
-                    if (k >= K) break;   // uniform per wavefront
-                    load_tile(tile_col(k + kSmAhead), k + kSmAhead < K,
-                              buf[(j + kSmAhead) % (kSmAhead + 1)]);
-                    const TileIn& cur = buf[j];
-                    const int c = c0 + (w + kSmWaves * k) * kSmTile;
+                    for (int j = 0; j <= kSmAhead; ++j) {
+                        const int k = kb + j;
+                        if (k >= K) break;   // uniform per wavefront
+                        load_tile(HR, HU, tile_col(k + kSmAhead), k + kSmAhead < K,
+                                  buf[(j + kSmAhead) % (kSmAhead + 1)]);
+                        const TileIn& cur = buf[j];
+                        const int c = c0 + (w + kSmWaves * k) * kSmTile;
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) {
-                        v4d acc = cur.b[rb];
-                        // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
-                        if (kp > 0) {
+                        for (int rb = 0; rb < RB; ++rb) {
+                            v4d acc = cur.b[rb];
+                            // B'^T = B^T + R^T (-Y)^T over the 32 moves (Y is zero past kp)
+                            if constexpr (decltype(HR)::value) {
 #pragma unroll
-                            for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
-                                acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
-                        }
-                        const int i = i0 + 16 * rb + lr;
-                        if (kp > 0 && i < n) {
-                            double* brow = inv + (int64_t)i * a.ld;
-                            if (VEC && c + kSmTile <= cend) {
-                                *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
-                                *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
-                            } else {
+                                for (int s4 = 0; s4 < kSmChunk / 4; ++s4)
+                                    acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
+                            }
+                            const int i = i0 + 16 * rb + lr;
+                            if (decltype(HR)::value && i < n) {
+                                double* brow = inv + (int64_t)i * a.ld;
+                                if (VEC && c + kSmTile <= cend) {
+                                    *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
+                                    *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
+                                } else {
+#pragma unroll
+                                    for (int r = 0; r < 4; ++r)
+                                        if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                                }
+                            }
+                            if (sl[rb] >= 0) {
 #pragma unroll
                                 for (int r = 0; r < 4; ++r)
-                                    if (c + cq + r < cend) brow[c + cq + r] = acc[r];
+                                    if (c + cq + r < cend) Rn[(int64_t)sl[rb] * n + c + cq + r] = acc[r];
                             }
-                        }
-                        if (sl[rb] >= 0) {
+                            // V += B' U^T, k-step r over the columns c + 4q + r
+                            // (columns past the tile contribute zero: both operands are
+                            // replaced, so that what was loaded there cannot reach V)
+                            if constexpr (decltype(HU)::value) {
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (c + cq + r < cend) Rn[(int64_t)sl[rb] * n + c + cq + r] = acc[r];
-                        }
-                        // V += B' U^T, k-step r over the columns c + 4q + r
-                        // (columns past the tile contribute zero: both operands are
-                        // replaced, so that what was loaded there cannot reach V)
-                        if (kn > 0) {
+                                for (int r = 0; r < 4; ++r) {
+                                    const bool in = c + cq + r < cend;
+                                    const double bval = in ? acc[r] : 0.0;
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const bool in = c + cq + r < cend;
-                                const double bval = in ? acc[r] : 0.0;
-#pragma unroll
-                                for (int mb = 0; mb < kSmMB; ++mb)
-                                    vacc[rb][mb] = mfma_f64_16x16x4(
-                                        bval, (double)(in ? cur.u[mb][r] : 0.0f), vacc[rb][mb]);
+                                    for (int mb = 0; mb < kSmMB; ++mb)
+                                        vacc[rb][mb] = mfma_f64_16x16x4(
+                                            bval, (double)(in ? cur.u[mb][r] : 0.0f), vacc[rb][mb]);
+                                }
                             }
                         }
                     }
                 }
             }
-        }
-        if (kn > 0) {
-            // element r of vacc[rb][mb] is V[row 16 rb + 4r + g][move 16 mb + lr]
+            if constexpr (decltype(HU)::value) {
+                // element r of vacc[rb][mb] is V[row 16 rb + 4r + g][move 16 mb + lr]
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+                for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int mb = 0; mb < kSmMB; ++mb)
+                    for (int mb = 0; mb < kSmMB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Vw[w][16 * rb + 4 * r + g][16 * mb + lr] = vacc[rb][mb][r];
-            __syncthreads();
-            for (int e = tid; e < ROWS * kSmChunk; e += kSmThreads) {
-                const int row = e / kSmChunk, m = e % kSmChunk;
-                double v = Vw[0][row][m];
+                        for (int r = 0; r < 4; ++r)
+                            Vw[w][16 * rb + 4 * r + g][16 * mb + lr] = vacc[rb][mb][r];
+                __syncthreads();
+                for (int e = tid; e < ROWS * kSmChunk; e += kSmThreads) {
+                    const int row = e / kSmChunk, m = e % kSmChunk;
+                    double v = Vw[0][row][m];
 #pragma unroll
-                for (int ww = 1; ww < kSmWaves; ++ww) v += Vw[ww][row][m];
-                if (i0 + row < n && m < kn)
-                    Pn[((int64_t)y * n + i0 + row) * kSmChunk + m] = v;
+                    for (int ww = 1; ww < kSmWaves; ++ww) v += Vw[ww][row][m];
+                    if (i0 + row < n && m < kn)
+                        Pn[((int64_t)y * n + i0 + row) * kSmChunk + m] = v;
+                }
+                __syncthreads();   // Vw is rewritten for the next column tile
             }
-            __syncthreads();   // Vw is rewritten for the next column tile
         }
-    }
+    };
+    if (kp > 0 && kn > 0)
+        walk(std::true_type{}, std::true_type{});
+    else if (kp > 0)
+        walk(std::true_type{}, std::false_type{});
+    else if (kn > 0)
+        walk(std::false_type{}, std::true_type{});
 }
 
 // The row count of a workgroup only distributes work: every element goes

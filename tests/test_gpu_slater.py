@@ -159,6 +159,26 @@ def test_padded_leading_dimensions(blip, ld, u_ld):
     np.testing.assert_allclose(to_np(r), want_r, rtol=1e-10)
 
 
+def test_wide_and_narrow_loads_agree_bitwise(blip):
+    """The same update with rows 16-byte aligned (16-byte tile loads) and
+    with odd leading dimensions (8- and 4-byte loads): bit for bit equal,
+    ratios included, and within the oracle's bar."""
+    n, ld = 72, 73
+    D, inv_t, cols, U = case(7, n, 50)
+    inv_a = torch.from_numpy(inv_t.copy()).cuda()
+    r_a = blip.sm_update(inv_a, torch.from_numpy(U).cuda(), cols)
+    wide = np.zeros((n, ld))
+    wide[:, :n] = inv_t
+    base = torch.from_numpy(wide).cuda()
+    Uw = np.zeros((n, ld), dtype=np.float32)
+    Uw[:, :n] = U
+    r_b = blip.sm_update(base[:, :n], torch.from_numpy(Uw).cuda()[:, :n], cols)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(base)[:, :n], to_np(inv_a))
+    np.testing.assert_array_equal(to_np(r_b), to_np(r_a))
+    check(blip, D, inv_t, cols, U, label="aligned rows")
+
+
 def test_quasi_simultaneous_step_tio2(blip):
     """One spin of the TiO2 block (768 electrons, 768 orbitals of the
     72x72x48 table): the Slater matrix from blip_eval at the old positions,
@@ -229,11 +249,13 @@ def test_batched_equals_single_bitwise(blip):
     np.testing.assert_allclose(got_r[q, : counts[q]], want_r, rtol=1e-9)
 
 
-def test_batched_two_row_blocks_equals_single_bitwise(blip):
+@pytest.mark.parametrize("n", [200, 201])
+def test_batched_two_row_blocks_equals_single_bitwise(blip, n):
     """Enough matrices for the batched kernel to take two 16-row blocks per
     workgroup (ceil(n/32) * nmat >= 1024): still bit for bit the single-matrix
-    result on sampled matrices, with a ragged n and uneven counts."""
-    n, nmat = 200, 160
+    result on sampled matrices, with a ragged n and uneven counts.  At
+    n = 201 the rows are not 16-byte aligned (8- and 4-byte tile loads)."""
+    nmat = 160
     rng = np.random.default_rng(23)
     D0, inv0, _, U0 = case(400, n, 1)
     invs = np.stack([inv0 * (1.0 + 0.01 * q) for q in range(nmat)])
