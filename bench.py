@@ -1007,6 +1007,38 @@ def bench_paper_sizes(args, cache, leg=None):
     return rows
 
 
+def stream_read_rate(nbytes=2 << 30, reps=10, grids=(1024, 2048, 4096, 8192, 16384, 32768, 65535)):
+    """Achievable HBM read rate on this GPU, the denominator the orbital
+    kernel's bound calls for: blip_stream_read over a 2 GiB buffer (more
+    than the Infinity Cache holds), event-timed, the best of a few grid
+    sizes.  Returns (GB/s, workgroups)."""
+    import torch
+    from paper_1204_1121_amd import blip
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    part = torch.empty(max(grids), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    best = (0.0, grids[0])
+    for nb in grids:
+        p = part[:nb]
+        for _ in range(2):
+            blip.stream_read(x, p)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            blip.stream_read(x, p)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3 / reps
+        if float(p.sum()) != nbytes // 4:
+            raise RuntimeError("stream read probe: partial sums do not cover the buffer")
+        log(f"stream read, {nb} workgroups: {nbytes / dt / 1e9:.0f} GB/s")
+        best = max(best, (nbytes / dt / 1e9, nb))
+    del x, part
+    return best
+
+
 def stream_copy_rate(nbytes=1 << 30, reps=10):
     """Achievable HBM rate on this GPU as a second denominator: a 1 GiB
     device-to-device copy (read plus write bytes over the event-timed copy),
@@ -1300,6 +1332,14 @@ def main():
                                  "tiled_kernel_traffic_frac_of_copy":
                                      traffic / t_kernel / 1e9 / g if traffic else None}
         log(f"stream copy {g:.0f} GB/s; tiled kernel at {achieved / g:.2f} of it (algorithmic bytes)")
+        rd, nb = stream_read_rate()
+        result["stream_read"] = {"gbs": rd, "bytes": 2 << 30, "workgroups": nb,
+                                 "frac_of_peak": rd / HBM_PEAK_GBS,
+                                 "tiled_kernel_frac_of_read": achieved / rd,
+                                 "tiled_kernel_traffic_frac_of_read":
+                                     traffic / t_kernel / 1e9 / rd if traffic else None}
+        log(f"stream read {rd:.0f} GB/s ({nb} workgroups); tiled kernel at {achieved / rd:.2f} "
+            f"of it (algorithmic bytes)")
 
     if leg is not None:
         log("timing the FP64 oracle on the host ...")

@@ -537,6 +537,24 @@ BLIP_API int blip_qs_lap_ratios(int64_t nrows, int len, const float* lap, int64_
                                const double* inv_rows, int64_t inv_ld, double* lap_ratio,
                                void* stream);
 
+/*
+ * blip_stream_read -- measurement helper: read a device buffer once,
+ * streaming, and write per-workgroup sums.  It gives the achievable HBM read
+ * rate on this GPU, the second denominator (beside the 8 TB/s peak) for the
+ * bandwidth fraction of the orbital evaluation, whose bound is the reading
+ * of coefficient rows (a gather-weighted sum, Eq. (7)).
+ *
+ *  buf      device memory, 16-byte aligned, read as float4.
+ *  bytes    a positive multiple of 16.
+ *  partial  device float[nblocks]: partial[b] = FP32 sum of the floats that
+ *           workgroup b read (the 32 KB pieces b, b + nblocks, ...), so that
+ *           the sum of all partials covers every element once.
+ *  nblocks  workgroups of 256 threads, 1..65535.
+ * Asynchronous on the stream, no allocation.  BLIP_E_ARG / BLIP_E_ALIGN.
+ */
+BLIP_API int blip_stream_read(const void* buf, size_t bytes, float* partial, int nblocks,
+                              void* stream);
+
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage,

@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
     L.blip_qs_copy_rows.argtypes = [ci, ci, ci, vp, i64, vp, vp, i64, vp, i64, vp]
     L.blip_qs_lap_ratios.restype = ci
     L.blip_qs_lap_ratios.argtypes = [i64, ci, vp, i64, vp, i64, vp, vp]
+    L.blip_stream_read.restype = ci
+    L.blip_stream_read.argtypes = [vp, ctypes.c_size_t, vp, ci, vp]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -514,6 +516,18 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+def stream_read(buf: torch.Tensor, partial: torch.Tensor, stream=None) -> None:
+    """One streaming read of the device buffer buf (blip_stream_read):
+    partial (cuda float32, one entry per workgroup) receives the sums of
+    what each workgroup read."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous CUDA tensor")
+    if partial.dtype != torch.float32 or not partial.is_cuda or not partial.is_contiguous():
+        raise ValueError("partial must be a contiguous CUDA float32 tensor")
+    check(lib().blip_stream_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partial),
+                                 partial.numel(), _stream_ptr(stream)))
 
 
 def sm_workspace(n: int, device="cuda") -> torch.Tensor:

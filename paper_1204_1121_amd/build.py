@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libblip.so")
 
 SOURCES = ["blip_launch_f32.hip", "blip_launch_bf16.hip", "blip_launch_f16.hip",
            "blip_table.hip", "blip_runtime.hip", "blip_batched.hip", "blip_slater.hip",
-           "blip_qs.hip"]
+           "blip_qs.hip", "blip_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -242,3 +242,18 @@ def test_qs_helpers_argument_errors(blip):
                None, dev, 1 << 20, None) == -5
     assert rvb(None, dev, dev, 1, 4, dev, 8, None, dev, None, None, dev, None, dev, 1 << 20,
                None) == -6
+
+
+def test_stream_read_argument_errors(blip):
+    """blip_stream_read checks sizes and alignment on the host (fake pointers,
+    never dereferenced)."""
+    L = blip.lib()
+    dev = ctypes.c_void_p(0x10000)
+    assert L.blip_stream_read(dev, 1 << 20, dev, 0, None) == -1
+    assert L.blip_stream_read(dev, 1 << 20, dev, 65536, None) == -1
+    assert L.blip_stream_read(dev, 0, dev, 8, None) == -1
+    assert L.blip_stream_read(dev, 24, dev, 8, None) == -1
+    assert L.blip_stream_read(None, 1 << 20, dev, 8, None) == -1
+    assert L.blip_stream_read(dev, 1 << 20, None, 8, None) == -1
+    assert L.blip_stream_read(ctypes.c_void_p(0x10008), 1 << 20, dev, 8, None) == -5
+    assert L.blip_stream_read(dev, 1 << 20, ctypes.c_void_p(0x10002), 8, None) == -5
