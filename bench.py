@@ -1039,6 +1039,46 @@ def stream_read_rate(nbytes=2 << 30, reps=10, grids=(1024, 2048, 4096, 8192, 163
     return best
 
 
+def scattered_read_rate(total_bytes, run_bytes=12288, row_bytes=3072, nbytes=768 << 20,
+                        reps=20, grids=(2048, 8192)):
+    """Read rate of one launch that reads total_bytes as runs of run_bytes
+    at random row-aligned offsets of a table-sized buffer (a block's
+    coefficient rows are runs of 4 rows along a3 at scattered offsets):
+    blip_stream_read_runs, event-timed, the best of a few grid sizes.
+    Returns (GB/s, us per launch, workgroups)."""
+    import torch
+    from paper_1204_1121_amd import blip
+    nruns = max(1, int(round(total_bytes / run_bytes)))
+    rng = np.random.default_rng(12041121)
+    offs = rng.integers(0, (nbytes - run_bytes) // row_bytes, nruns) * row_bytes
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    doff = torch.from_numpy(offs.astype(np.int64)).cuda()
+    part = torch.empty(max(grids), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    best = (0.0, 0.0, grids[0])
+    for nb in grids:
+        p = part[:nb]
+        for _ in range(3):
+            blip.stream_read_runs(buf, doff, run_bytes, p)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            blip.stream_read_runs(buf, doff, run_bytes, p)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) * 1e-3 / reps
+        if float(p.sum()) != nruns * run_bytes // 4:
+            raise RuntimeError("scattered read probe: partial sums do not cover the runs")
+        rate = nruns * run_bytes / dt / 1e9
+        log(f"scattered read, {nb} workgroups: {rate:.0f} GB/s, {dt * 1e6:.1f} us per launch")
+        if rate > best[0]:
+            best = (rate, dt * 1e6, nb)
+    del buf, doff, part
+    return best
+
+
 def stream_copy_rate(nbytes=1 << 30, reps=10):
     """Achievable HBM rate on this GPU as a second denominator: a 1 GiB
     device-to-device copy (read plus write bytes over the event-timed copy),
@@ -1340,6 +1380,15 @@ def main():
                                      traffic / t_kernel / 1e9 / rd if traffic else None}
         log(f"stream read {rd:.0f} GB/s ({nb} workgroups); tiled kernel at {achieved / rd:.2f} "
             f"of it (algorithmic bytes)")
+        moved = traffic if traffic else b_gather
+        sr, sus, snb = scattered_read_rate(moved)
+        result["scattered_read"] = {
+            "gbs": sr, "us_per_launch": sus, "workgroups": snb, "run_bytes": 12288,
+            "bytes_per_launch": moved,
+            "bytes_from": "kernel counters" if traffic else "no-reuse gather count",
+            "tiled_kernel_time_frac": sus / (t_kernel * 1e6)}
+        log(f"scattered read of {moved / 1e6:.0f} MB in 12 KB runs: {sr:.0f} GB/s, {sus:.1f} us; "
+            f"tiled kernel takes {t_kernel * 1e6 / sus:.2f}x that")
 
     if leg is not None:
         log("timing the FP64 oracle on the host ...")

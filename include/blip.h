@@ -555,6 +555,28 @@ BLIP_API int blip_qs_lap_ratios(int64_t nrows, int len, const float* lap, int64_
 BLIP_API int blip_stream_read(const void* buf, size_t bytes, float* partial, int nblocks,
                               void* stream);
 
+/*
+ * blip_stream_read_runs -- measurement helper, scattered form: read runs of
+ * run_bytes contiguous bytes at the given offsets, the access pattern of a
+ * block's coefficient rows (the 4 rows along a3 of a stencil line are one
+ * run of 4 L floats at a scattered offset, Eq. (7)).  It gives the read rate
+ * such a launch can reach, the ceiling for the orbital kernel's traffic.
+ *
+ *  buf          device memory of `bytes` bytes (a positive multiple of 16),
+ *               16-byte aligned.
+ *  run_offsets  device int64[nruns], byte offsets of the runs.  A run that is
+ *               not 16-byte aligned or does not lie inside the buffer is
+ *               skipped (never read out of bounds).
+ *  run_bytes    4096, 8192, 12288, 16384, 24576 or 49152.
+ *  partial      device float[nblocks]: partial[b] = FP32 sum of the floats
+ *               of the runs b, b + nblocks, ... that workgroup b read.
+ *  nblocks      workgroups of 256 threads, 1..65535.
+ * Asynchronous on the stream, no allocation.  BLIP_E_ARG / BLIP_E_ALIGN.
+ */
+BLIP_API int blip_stream_read_runs(const void* buf, size_t bytes, const int64_t* run_offsets,
+                                   int nruns, int run_bytes, float* partial, int nblocks,
+                                   void* stream);
+
 /* blip_table_info -- describe a table: L, storage dtype, row stride in bytes,
  * total device bytes.  Any output pointer may be NULL. */
 BLIP_API int blip_table_info(blip_table t, int* norb, int* storage,

@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
     L.blip_qs_lap_ratios.argtypes = [i64, ci, vp, i64, vp, i64, vp, vp]
     L.blip_stream_read.restype = ci
     L.blip_stream_read.argtypes = [vp, ctypes.c_size_t, vp, ci, vp]
+    L.blip_stream_read_runs.restype = ci
+    L.blip_stream_read_runs.argtypes = [vp, ctypes.c_size_t, vp, ci, ci, vp, ci, vp]
     L.blip_table_info.restype = ci
     L.blip_table_info.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -528,6 +530,21 @@ def stream_read(buf: torch.Tensor, partial: torch.Tensor, stream=None) -> None:
         raise ValueError("partial must be a contiguous CUDA float32 tensor")
     check(lib().blip_stream_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partial),
                                  partial.numel(), _stream_ptr(stream)))
+
+
+def stream_read_runs(buf: torch.Tensor, offsets: torch.Tensor, run_bytes: int,
+                     partial: torch.Tensor, stream=None) -> None:
+    """Read runs of run_bytes bytes of buf at the byte offsets (cuda int64)
+    (blip_stream_read_runs); partial receives per-workgroup sums."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous CUDA tensor")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous CUDA int64 tensor")
+    if partial.dtype != torch.float32 or not partial.is_cuda or not partial.is_contiguous():
+        raise ValueError("partial must be a contiguous CUDA float32 tensor")
+    check(lib().blip_stream_read_runs(_ptr(buf), buf.numel() * buf.element_size(), _ptr(offsets),
+                                      offsets.numel(), run_bytes, _ptr(partial), partial.numel(),
+                                      _stream_ptr(stream)))
 
 
 def sm_workspace(n: int, device="cuda") -> torch.Tensor:

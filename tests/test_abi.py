@@ -257,3 +257,23 @@ def test_stream_read_argument_errors(blip):
     assert L.blip_stream_read(dev, 1 << 20, None, 8, None) == -1
     assert L.blip_stream_read(ctypes.c_void_p(0x10008), 1 << 20, dev, 8, None) == -5
     assert L.blip_stream_read(dev, 1 << 20, ctypes.c_void_p(0x10002), 8, None) == -5
+
+
+def test_stream_read_runs_argument_errors(blip):
+    """blip_stream_read_runs checks sizes, the run length and alignment on the
+    host (fake pointers, never dereferenced)."""
+    L = blip.lib()
+    dev = ctypes.c_void_p(0x10000)
+    MB = 1 << 20
+
+    def call(buf=dev, nbytes=MB, off=dev, nruns=4, rb=12288, part=dev, nb=8):
+        return L.blip_stream_read_runs(buf, nbytes, off, nruns, rb, part, nb, None)
+
+    assert call(nb=0) == -1 and call(nb=65536) == -1
+    assert call(nruns=-1) == -1
+    assert call(nbytes=0) == -1 and call(nbytes=40) == -1
+    assert call(rb=4000) == -1 and "run_bytes" in L.blip_last_error().decode()
+    assert call(off=None) == -1 and call(buf=None) == -1 and call(part=None) == -1
+    assert call(buf=ctypes.c_void_p(0x10008)) == -5
+    assert call(off=ctypes.c_void_p(0x10004)) == -5
+    assert call(part=ctypes.c_void_p(0x10002)) == -5

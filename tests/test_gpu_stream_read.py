@@ -38,3 +38,26 @@ def test_every_element_read_once(blip, n, nblocks):
     got = part.cpu().numpy().astype(np.float64).sum()
     want = x.astype(np.float64).sum()
     assert abs(got - want) <= 1e-5 * want
+
+
+@pytest.mark.parametrize("run_bytes", [4096, 12288, 49152])
+def test_runs_read_what_they_name(blip, run_bytes):
+    """The scattered form reads exactly the named runs (overlapping runs
+    count twice), and skips runs that are misaligned or past the end."""
+    n = 1 << 20
+    rng = np.random.default_rng(run_bytes)
+    x = rng.integers(0, 8, n).astype(np.float32)
+    buf = torch.from_numpy(x).cuda()
+    nb = n * 4
+    good = rng.integers(0, (nb - run_bytes) // 16, 300) * 16
+    bad = np.array([-16, 8, nb - run_bytes + 16, nb], dtype=np.int64)
+    offs = np.concatenate([good, bad]).astype(np.int64)
+    rng.shuffle(offs)
+    part = torch.zeros(64, dtype=torch.float32, device="cuda")
+    say(f"scattered read: {len(good)} runs of {run_bytes} B and {len(bad)} to skip")
+    blip.stream_read_runs(buf, torch.from_numpy(offs).cuda(), run_bytes, part)
+    torch.cuda.synchronize()
+    w = run_bytes // 4
+    want = sum(float(x[o // 4: o // 4 + w].astype(np.float64).sum()) for o in good)
+    got = float(part.cpu().numpy().astype(np.float64).sum())
+    assert got == want          # integers: every partial below 2^24, exact
