@@ -800,6 +800,39 @@ def bench_vmc(args, table, spec, leg=None, cache=None):
     log(f"vmc: {t_step * 1e6:.0f} us per quasi-simultaneous step of {W} walkers x {2 * n} "
         f"electrons ({W / t_step:.0f} walker-steps/s, acceptance {acc:.2f})")
 
+    # -- two sets of W walkers, each on its own stream, stepped in turn: one
+    # set's latency-bound inverse updates overlap the other's ratio pass
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sets = []
+    for k, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            p0 = torch.rand((W, 2 * n, 3), dtype=torch.float64, device="cuda", generator=g) @ lat
+        sets.append(vmc.Walkers(table, p0, stream=st))
+    torch.cuda.synchronize()
+    for i in range(3):
+        for wk2 in sets:
+            wk2.step(etas[i % 4], unis[i % 4])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for st in streams:
+        st.wait_event(e0)
+    for i in range(steps):
+        for wk2 in sets:
+            wk2.step(etas[i % 4], unis[i % 4])
+    for st in streams:
+        stream.wait_stream(st)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_pair = e0.elapsed_time(e1) * 1e-3 / steps
+    res["two_sets_two_streams"] = {"walkers_per_set": W, "sets": 2, "us_per_step_pair": t_pair * 1e6,
+                                   "walker_steps_per_s": 2 * W / t_pair,
+                                   "gain_over_one_set": (2 * W / t_pair) / (W / t_step)}
+    del sets
+    log(f"vmc: two sets of {W} walkers on two streams: {t_pair * 1e6:.0f} us per step pair "
+        f"({2 * W / t_pair:.0f} walker-steps/s)")
+
     if args.no_vmc_stats:
         return res
     # -- statistics: quasi-simultaneous against particle-by-particle
