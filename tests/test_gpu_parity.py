@@ -242,11 +242,23 @@ def tio2(blip):
 
 @pytest.mark.parametrize("B", [1, 8, 64, 1536])
 def test_tio2_blocks(tio2, B):
+    """The C1 block sizes against the oracle: the tiled kernel at the
+    default shape and at the launch shape the benchmark runs (the package's
+    tuning cache; the same arithmetic per element, so bit for bit the same
+    outputs), the plain and the site-parallel kernels."""
+    from paper_1204_1121_amd.tuning import TuneCache
     spec, c, t = tio2
     pos = wl.move_block(spec, B, block=0)
     say(f"TiO2 block B={B}")
     ref = oracle.evaluate(spec.lattice, spec.n, c, pos, nthreads=8)
-    check(gpu_eval(t, pos), ref, FP32_TOL, "tuned")
+    y = gpu_eval(t, pos)
+    check(y, ref, FP32_TOL, "default shape")
+    e = TuneCache().get(t, B)
+    if e is not None:
+        yt = gpu_eval(t, pos, kernel="tiled", tile_pos=e["tile_pos"], vec=e["vec"])
+        check(yt, ref, FP32_TOL, f"benchmark shape ({e['tile_pos']}, {e['vec']})")
+        for k in ("val", "grad", "lap"):
+            np.testing.assert_array_equal(yt[k], y[k], err_msg=f"{k}: shapes differ")
     check(gpu_eval(t, pos, kernel="plain"), ref, FP32_TOL, "plain")
     check(gpu_eval(t, pos, kernel="site"), ref, FP32_TOL, "site-parallel")
 
