@@ -200,6 +200,26 @@ def test_tio2_512_walkers(blip):
     ye = np_out(t.eval(p))
     for k in yb:
         np.testing.assert_array_equal(yb[k], ye[k])
+    # the launch the benchmark times: a plan at the package's cached batched
+    # shape, restored as the benchmark restores it (for the largest of its
+    # four batches; a smaller size takes the adjacent bucket's shape)
+    from paper_1204_1121_amd.tuning import TuneCache
+    npos = b.pos.shape[0]
+    cap = max(wl.walker_batch(spec, nwalkers=512, max_block=256, batch=q).pos.shape[0]
+              for q in range(4))
+    if TuneCache().apply(t, cap, batched=True):
+        say(f"  cached batched shape {t.get_shape(npos, batched=True)}, plan replay")
+        out = t.alloc_outputs(npos)
+        plan = t.plan(p, o, out, t.workspace(npos), capacity=npos)
+        for _ in range(2):
+            for x in out:
+                x.zero_()
+            torch.cuda.synchronize()
+            plan.launch()
+            torch.cuda.synchronize()
+            for k, v in zip(("val", "grad", "lap"), out):
+                np.testing.assert_array_equal(to_np(v), ye[k], err_msg=f"plan replay, {k}")
+        plan.free()
     idx = np.random.default_rng(0).choice(b.pos.shape[0], 512, replace=False)
     ref = oracle.evaluate(spec.lattice, spec.n, c, b.pos[idx], nthreads=8)
     e = group_errors({k: v[idx] for k, v in yb.items()}, ref)
