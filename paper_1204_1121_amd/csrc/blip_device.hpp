@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace blip {
 
 constexpr int kWave = 64;
@@ -350,20 +352,23 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
 #pragma unroll
         for (int e = 0; e < OE; ++e) out[q][e] = (ACC)0;
 
-    // Slab m1 (4x4 rows) is loaded one iteration ahead: while slab m1 is
-    // summed, the 16 loads of slab m1+1 are already in flight.
+    // Row group m2 of slab m1: the 4 rows along a3 of line (m1, m2).
+    auto load_group = [&](int m1, int m2, ACC (&xg)[4][OE]) {
+        const uint64_t ob = (uint64_t)uniform_u(pp.rb[m1 * 4 + m2]) * (uint64_t)row_bytes;
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char*>(coef) + ob, 0, line_bytes, kBufWord3);
+#pragma unroll
+        for (int m3 = 0; m3 < 4; ++m3)
+            load_elems_buf<E, OE, ACC>(r, voff, off3[m3], xg[m3]);
+    };
     auto load_slab = [&](int m1, ACC (&x)[4][4][OE]) {
 #pragma unroll
-        for (int m2 = 0; m2 < 4; ++m2) {
-            const uint64_t ob = (uint64_t)uniform_u(pp.rb[m1 * 4 + m2]) * (uint64_t)row_bytes;
-            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<char*>(coef) + ob, 0, line_bytes, kBufWord3);
-#pragma unroll
-            for (int m3 = 0; m3 < 4; ++m3)
-                load_elems_buf<E, OE, ACC>(r, voff, off3[m3], x[m2][m3]);
-        }
+        for (int m2 = 0; m2 < 4; ++m2) load_group(m1, m2, x[m2]);
     };
-    auto sum_slab = [&](int m1, const ACC (&x)[4][4][OE]) {
+    // Sums slab m1 held in x.  With REFILL, each row group of x is reloaded
+    // with slab m1+1's as soon as its inner sums are formed: one buffer, no
+    // copies, and the next slab's loads spread over this slab's sums.
+    auto sum_slab = [&](int m1, ACC (&x)[4][4][OE], auto REFILL) {
         ACC w1[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) w1[k] = uniform_f(pp.w[0][k][m1]);
@@ -409,6 +414,7 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
                     }
                 }
             }
+            if constexpr (decltype(REFILL)::value) load_group(m1 + 1, m2, x[m2]);
         }
 #pragma unroll
         for (int e = 0; e < OE; ++e) {
@@ -444,22 +450,13 @@ __device__ __forceinline__ void gather_item(const char* __restrict__ coef, int v
 #pragma unroll
         for (int m1 = 0; m1 < 4; ++m1) load_slab(m1, xa[m1]);
 #pragma unroll
-        for (int m1 = 0; m1 < 4; ++m1) sum_slab(m1, xa[m1]);
+        for (int m1 = 0; m1 < 4; ++m1) sum_slab(m1, xa[m1], std::false_type{});
     } else {
-        ACC xn[4][4][OE];
-        load_slab(0, xn);
+        ACC x[4][4][OE];
+        load_slab(0, x);
 #pragma unroll 1
-        for (int m1 = 0; m1 < 4; ++m1) {
-            ACC x[4][4][OE];
-#pragma unroll
-            for (int m2 = 0; m2 < 4; ++m2)
-#pragma unroll
-                for (int m3 = 0; m3 < 4; ++m3)
-#pragma unroll
-                    for (int e = 0; e < OE; ++e) x[m2][m3][e] = xn[m2][m3][e];
-            if (m1 < 3) load_slab(m1 + 1, xn);
-            sum_slab(m1, x);
-        }
+        for (int m1 = 0; m1 < 3; ++m1) sum_slab(m1, x, std::true_type{});
+        sum_slab(3, x, std::false_type{});
     }
 }
 
