@@ -221,13 +221,13 @@ def test_result_alone_equals_result_in_the_mix():
             np.testing.assert_array_equal(r.result[k], alone[k])
 
 
-def test_open_loop_driver_reports_latency():
+def test_open_loop_run_reports_latency():
     clock = FakeClock()
     be = FakeBackend(clock, make_systems(), capacity=100, max_requests=8, slots=2)
     sv = Server(be, budget_bytes=10 ** 9, clock=clock)
     reqs = [req(i, i % 2, 3, t=i * 1e-3) for i in range(30)]
 
-    # the fake clock advances by itself as the driver polls it
+    # the fake clock advances by itself each time the server reads it
     def tick():
         clock.advance(2e-5)
         return clock.t
