@@ -356,16 +356,17 @@ class GpuBackend:
         hp = sl["hpos_np"]
         # the staging buffers are reused only after this slot's previous
         # launch completed (the scheduler frees a slot on completion)
-        row = 0
-        for r in reqs:
-            k = r.npos
-            hp[row:row + k] = r.pos
-            row += k
+        # one packing call for the whole launch (a slice assignment per
+        # request cost about a microsecond each at saturation)
+        counts = [r.npos for r in reqs]
+        row = sum(counts)
+        if reqs:
+            np.concatenate([r.pos for r in reqs], axis=0, out=hp[:row])
         sorted_plan = self.batched and row >= self.sort_threshold
         if sorted_plan:
             ho = sl["hoff_np"]
             ho[0] = 0
-            ho[1:len(reqs) + 1] = np.cumsum([r.npos for r in reqs])
+            ho[1:len(reqs) + 1] = np.cumsum(counts)
             ho[len(reqs) + 1:] = row
             self.sorted_launches += 1
         else:
