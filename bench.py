@@ -348,7 +348,7 @@ def bench_sm(args, leg=None):
     _, tb = time_region(step_b, [None], steps_b, 2, stream)
     res["batched"] = {"matrices": nmat, "us_per_step": tb * 1e6,
                       "us_per_matrix_step": tb * 1e6 / nmat,
-                      "launches_per_step": 2 * ((K + 31) // 32) + 1,
+                      "launches_per_step": 2 * ((K + 31) // 32) + 2,
                       "tflops_fp64": nmat * flop / tb / 1e12,
                       "frac_fp64_peak": nmat * flop / tb / 1e12 / FP64_PEAK_TFLOPS}
     del inv_b, u_b, ws_b

@@ -457,10 +457,10 @@ BLIP_API size_t blip_sm_workspace_size(int64_t n);
  *              per matrix (a quasi-simultaneous step moves each once).
  *  acc_count   device int32 [nmat]: moves of matrix q, clamped to [0, max_k].
  *  max_k       host bound on every count (0..n); sets the number of launches,
- *              2 * ceil(max_k / 32) + 1, whatever the counts are.
+ *              2 * ceil(max_k / 32) + 2, whatever the counts are.
  *  ratios      device double [nmat][ratio_ld] or NULL: the sequential ratios,
  *              slot m of matrix q for its move m.
- *  workspace   blip_sm_batched_workspace_size(nmat, n) bytes, 8-byte aligned.
+ *  workspace   blip_sm_batched_workspace_size(nmat, n) bytes, 16-byte aligned.
  * Entries of acc_cols outside [0, n) are clamped into it: wrong input gives
  * wrong results, never an out-of-bounds access; a repeated electron within a
  * matrix gives wrong results.  The arithmetic and its order are exactly those

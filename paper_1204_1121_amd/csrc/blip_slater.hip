@@ -95,6 +95,11 @@ struct SmArgs {
     int* act;                // [1 + nmat] matrices with moves in the launch, from it
     uint32_t inv_bytes;      // bytes of B (of one matrix) the tile loads may touch
     uint32_t u_bytes;        // bytes of u (of one matrix) the tile loads may touch
+    // Batched form: the new orbital rows of a chunk packed tile by tile,
+    // [column tile][move][16 columns] floats, two chunks per matrix in its
+    // workspace block (chunk c in buffer c % 2); upk is matrix 0's buffer 0.
+    float* upk;
+    uint32_t pk_bytes;       // bytes of one packed chunk
 };
 
 // Column tiles: at most kSmMaxTiles per row (so summing V's partials stays
@@ -114,10 +119,20 @@ inline SmShape sm_shape(int64_t n)
 // then S^{-1} of the applied chunk (padded rows).
 constexpr int64_t kSinvDoubles = kSmChunk * kSmPad;
 
-inline int64_t sm_ws_doubles(int64_t n)
+// Floats of one packed chunk of u: every 16-column tile of the 32 moves' rows.
+inline int64_t sm_pk_floats(int64_t n) { return (n + kSmTile - 1) / kSmTile * kSmChunk * kSmTile; }
+
+// Doubles before the packed chunks in a matrix's block (an even number, so
+// the packed chunks are 16-byte aligned).
+inline int64_t sm_pk_offset(int64_t n)
 {
     const SmShape sh = sm_shape(n);
-    const int64_t d = 2 * ((int64_t)sh.nct + 1) * kSmChunk * n + kSinvDoubles;
+    return 2 * ((int64_t)sh.nct + 1) * kSmChunk * n + kSinvDoubles;
+}
+
+inline int64_t sm_ws_doubles(int64_t n)
+{
+    const int64_t d = sm_pk_offset(n) + sm_pk_floats(n);   // two packed chunks of floats
     return (d + 31) / 32 * 32;   // keep each matrix's block 256-byte aligned
 }
 
@@ -182,6 +197,44 @@ __device__ __forceinline__ int sm_batched_col(const SmArgs& a, int q, int ch, in
 {
     const int c = a.acc_cols[(int64_t)q * a.acc_ld + (int64_t)ch * kSmChunk + m];
     return c < 0 ? 0 : (c >= a.n ? a.n - 1 : c);
+}
+
+// Moves of chunk ch of matrix q in a batched update.
+__device__ __forceinline__ int sm_chunk_moves(const SmArgs& a, int q, int ch)
+{
+    int cnt = a.acc_count[q];
+    cnt = cnt < 0 ? 0 : (cnt > a.max_k ? a.max_k : cnt);
+    return min(max(cnt - ch * kSmChunk, 0), kSmChunk);
+}
+
+// Packs column tile t of chunk ch (kc >= 1 moves) of matrix q: threads
+// 0..127 copy the 16 columns of move tid/4 (moves past kc repeat the last
+// one, as the tile loads of an unpacked u do), four floats each; columns past
+// n are zero.  The chunk kernel then reads a tile's u values as contiguous
+// 1 KB pieces instead of 16 pieces of 64 bytes from 16 rows.
+template <bool VEC>
+__device__ __forceinline__ void sm_pack_tile(const SmArgs& a, int q, int ch, int kc, int t, int tid)
+{
+    if (tid >= kSmChunk * kSmTile / 4) return;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int m = tid >> 2, j = tid & 3;
+    const int row = sm_batched_col(a, q, ch, m < kc ? m : kc - 1);
+    const int col = t * kSmTile + 4 * j;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(a.u + q * a.u_mstride), 0, a.u_bytes, kBufWord3);
+    const int o = (int)((row * a.u_ld + col) * (int64_t)sizeof(float));
+    f4 x;
+    if constexpr (VEC) {
+        x = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            x[r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o + 4 * r, 0, 0));
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = col + r < a.n ? x[r] : 0.0f;
+    float* dst = a.upk + q * 2 * a.ws_mstride + (ch & 1) * (a.pk_bytes / sizeof(float));
+    *reinterpret_cast<f4*>(dst + ((int64_t)t * kSmChunk + m) * kSmTile + 4 * j) = x;
 }
 
 // S = V[c_m][m'] of the applied chunk, the column-tile partials summed in a
@@ -431,6 +484,15 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         Rp += wo;
         Pn += wo;
         Rn += wo;
+        // the workgroups of the first column range pack the u rows of the
+        // chunk that the next launch prepares, one column tile each per row
+        // block
+        const int kn2 = sm_chunk_moves(a, q, a.chunk + 1);
+        if (kn2 > 0 && y0 == 0) {
+            const int nrb = (n + ROWS - 1) / ROWS;
+            const int ntp = (n + kSmTile - 1) / kSmTile;
+            for (int t = rblk; t < ntp; t += nrb) sm_pack_tile<VEC>(a, q, a.chunk + 1, kn2, t, tid);
+        }
     }
     const int i0 = rblk * ROWS;
 
@@ -563,12 +625,20 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // no memory traffic.
     const int bytes_b = (int)a.inv_bytes;
     const int bytes_r = kp > 0 ? kp * n * (int)sizeof(double) : 0;
-    const int bytes_u = kn > 0 ? (int)a.u_bytes : 0;
+    // the batched form reads u as the previous launch (or the pack launch
+    // before the first) packed it: the 32 moves' values of a column tile
+    // are 2 KB in a row, lane (lr, g) taking move 16 mb + lr, columns 4g..4g+3
+    const float* ubase = u;
+    if constexpr (BATCHED)
+        ubase = a.upk + q * 2 * a.ws_mstride + (a.chunk & 1) * (a.pk_bytes / sizeof(float));
+    const int bytes_u = kn > 0 ? (int)(BATCHED ? a.pk_bytes : a.u_bytes) : 0;
     int boff[RB], uoff[kSmMB];   // byte offsets of the lane's rows
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) boff[rb] = (int)(irow[rb] * a.ld * (int64_t)sizeof(double));
 #pragma unroll
-    for (int mb = 0; mb < kSmMB; ++mb) uoff[mb] = (int)(urow[mb] * a.u_ld * (int64_t)sizeof(float));
+    for (int mb = 0; mb < kSmMB; ++mb)
+        uoff[mb] = BATCHED ? ((16 * mb + lr) * kSmTile + cq) * (int)sizeof(float)
+                           : (int)(urow[mb] * a.u_ld * (int64_t)sizeof(float));
     // moved row 4 s4 + g at the column of slot lr (rows past kp read zero)
     const int roff = ((4 * (lr & 3) + (lr >> 2)) + g * n) * (int)sizeof(double);
     // HR, HU: std::bool_constant, whether R and u are present (kp > 0,
@@ -579,7 +649,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         const __amdgpu_buffer_rsrc_t rs_r = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<double*>(Rp), 0, live ? bytes_r : 0, kBufWord3);
         const __amdgpu_buffer_rsrc_t rs_u = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float*>(u), 0, live ? bytes_u : 0, kBufWord3);
+            const_cast<float*>(ubase), 0, live ? bytes_u : 0, kBufWord3);
         const int c8 = c * (int)sizeof(double);
         const int c4 = c * (int)sizeof(float);
 #pragma unroll
@@ -606,8 +676,9 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
         if constexpr (!decltype(HU)::value) return;
 #pragma unroll
         for (int mb = 0; mb < kSmMB; ++mb) {
-            const int o = uoff[mb] + c4 + cq * (int)sizeof(float);
-            if constexpr (VEC) {
+            const int o = BATCHED ? uoff[mb] + c * kSmChunk * (int)sizeof(float)
+                                  : uoff[mb] + c4 + cq * (int)sizeof(float);
+            if constexpr (VEC || BATCHED) {
                 const f4 x = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs_u, o, 0, 0));
                 in.u[mb][0] = x.x;
                 in.u[mb][1] = x.y;
@@ -756,6 +827,18 @@ __global__ __launch_bounds__(kSmThreads) __attribute__((amdgpu_waves_per_eu(2, 8
 void sm_chunk_batched_kernel(SmArgs a)
 {
     sm_chunk_body<true, RB, VEC>(a);
+}
+
+// Packs the u rows of the first chunk of every matrix (each later chunk is
+// packed by the launch before the one that reads it): workgroup (t, q) takes
+// column tile t of matrix q.
+template <bool VEC>
+__global__ __launch_bounds__(kSmChunk * kSmTile / 4) void sm_pack_kernel(SmArgs a)
+{
+    const int q = blockIdx.y, t = blockIdx.x;
+    const int kc = sm_chunk_moves(a, q, 0);
+    if (kc == 0) return;   // uniform over the workgroup
+    sm_pack_tile<VEC>(a, q, 0, kc, t, threadIdx.x);
 }
 
 hipError_t sm_launch(const SmArgs& a, bool vec, hipStream_t s)
@@ -921,9 +1004,9 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
         return fail(BLIP_E_ARG, "one matrix of inv (inv_ld = %lld) or of u (u_ld = %lld) spans "
                     "2 GiB or more", (long long)inv_ld, (long long)u_ld);
     if (!aligned(inv, 8) || !aligned(u, 4) || !aligned(acc_cols, 4) || !aligned(acc_count, 4) ||
-        (ratios && !aligned(ratios, 8)) || !aligned(workspace, 8))
-        return fail(BLIP_E_ALIGN, "inv, ratios and workspace need 8-byte, u and lists 4-byte "
-                                  "alignment");
+        (ratios && !aligned(ratios, 8)) || !aligned(workspace, 16))
+        return fail(BLIP_E_ALIGN, "workspace needs 16-byte, inv and ratios 8-byte, u and lists "
+                                  "4-byte alignment");
     const size_t need = blip_sm_batched_workspace_size(nmat, n);
     if (workspace == nullptr || workspace_bytes < need)
         return fail(BLIP_E_ARG, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
@@ -966,6 +1049,17 @@ BLIP_API int blip_sm_update_batched(int nmat, int64_t n, double* inv, int64_t in
     a.sinv = S;
     a.nmat = nmat;
     a.act = reinterpret_cast<int*>(static_cast<double*>(workspace) + (size_t)nmat * ws_m);
+    a.upk = reinterpret_cast<float*>(ws + sm_pk_offset(n));
+    a.pk_bytes = (uint32_t)(sm_pk_floats(n) * sizeof(float));
+    {
+        const dim3 pgrid((unsigned)((n + kSmTile - 1) / kSmTile), (unsigned)nmat);
+        if (vec)
+            hipLaunchKernelGGL(sm_pack_kernel<true>, pgrid, dim3(kSmChunk * kSmTile / 4), 0, s, a);
+        else
+            hipLaunchKernelGGL(sm_pack_kernel<false>, pgrid, dim3(kSmChunk * kSmTile / 4), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "sm_pack_kernel launch");
+    }
     // launch c applies chunk c-1 (S^{-1} from the launch of sm_sinv_kernel
     // just before it) and prepares chunk c
     for (int c = 0; c <= nchunks; ++c) {

@@ -174,7 +174,7 @@ def test_sm_update_batched_argument_errors(blip):
     assert call(w=None) == -1 and call(wb=ws - 1) == -1
     assert call(inv=ctypes.c_void_p(0x10004)) == -5
     assert call(cols=ctypes.c_void_p(0x10002)) == -5
-    assert call(w=ctypes.c_void_p(0x10004)) == -5
+    assert call(w=ctypes.c_void_p(0x10004)) == -5 and call(w=ctypes.c_void_p(0x10008)) == -5
     assert call(nmat=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
     assert call(max_k=0, inv=None, u=None, cols=None, cnt=None, w=None, wb=0) == 0
     big = (1 << 31) // (8 * (n - 1)) + 1
