@@ -416,7 +416,9 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     __shared__ double Vl[ROWS][kSmChunk];       // rows of V - E of this tile
     __shared__ double Y[ROWS][kSmChunk];        // rows of (V - E) S^{-1}
     __shared__ double piv[kSmChunk];
-    __shared__ double Vw[kSmWaves][ROWS][kSmChunk + 1];   // per-wavefront partial V
+    // per-wavefront partial V; during the walk, each wavefront's slice
+    // stages the B' tile it stores
+    __shared__ __attribute__((aligned(16))) double Vw[kSmWaves][ROWS][kSmChunk + 1];
     __shared__ int lcolp[kSmChunk], lcoln[kSmChunk], lurow[kSmChunk];
     __shared__ int slot[ROWS];                  // row's index in the next chunk, or -1
 
@@ -742,16 +744,29 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
                                     acc = mfma_f64_16x16x4(cur.r[s4], yop[rb][s4], acc);
                             }
                             const int i = i0 + 16 * rb + lr;
-                            if (decltype(HR)::value && i < n) {
+                            if (decltype(HR)::value && VEC && c + kSmTile <= cend) {
+                                // A lane holds 32 bytes of one row; stored as they
+                                // are, each 16-byte store instruction covers half of
+                                // 16 lines.  Passed through the wavefront's LDS slice,
+                                // 8 lanes store a whole 128-byte line: lane l takes
+                                // columns 2 (l%8), +1 of rows l/8 and l/8 + 8.
+                                constexpr int SLD = kSmTile + 2;   // staging row stride (doubles)
+                                double* st = &Vw[w][0][0];
+                                *reinterpret_cast<d2*>(st + lr * SLD + cq) = d2{acc[0], acc[1]};
+                                *reinterpret_cast<d2*>(st + lr * SLD + cq + 2) = d2{acc[2], acc[3]};
+                                __builtin_amdgcn_wave_barrier();
+                                const int sr = lane >> 3, sc = 2 * (lane & 7);
+                                const d2 x0 = *reinterpret_cast<const d2*>(st + sr * SLD + sc);
+                                const d2 x1 = *reinterpret_cast<const d2*>(st + (sr + 8) * SLD + sc);
+                                __builtin_amdgcn_wave_barrier();
+                                const int ia = i0 + 16 * rb + sr, ib = ia + 8;
+                                if (ia < n) *reinterpret_cast<d2*>(inv + (int64_t)ia * a.ld + c + sc) = x0;
+                                if (ib < n) *reinterpret_cast<d2*>(inv + (int64_t)ib * a.ld + c + sc) = x1;
+                            } else if (decltype(HR)::value && i < n) {
                                 double* brow = inv + (int64_t)i * a.ld;
-                                if (VEC && c + kSmTile <= cend) {
-                                    *reinterpret_cast<d2*>(brow + c + cq) = d2{acc[0], acc[1]};
-                                    *reinterpret_cast<d2*>(brow + c + cq + 2) = d2{acc[2], acc[3]};
-                                } else {
 #pragma unroll
-                                    for (int r = 0; r < 4; ++r)
-                                        if (c + cq + r < cend) brow[c + cq + r] = acc[r];
-                                }
+                                for (int r = 0; r < 4; ++r)
+                                    if (c + cq + r < cend) brow[c + cq + r] = acc[r];
                             }
                             if (sl[rb] >= 0) {
 #pragma unroll
