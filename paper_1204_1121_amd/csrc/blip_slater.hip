@@ -30,8 +30,10 @@
 // and is latency-bound: every workgroup eliminates S itself, which costs less
 // than another launch.  blip_sm_update_batched serves many matrices (walkers
 // and spins): a workgroup per matrix eliminates S once (sm_sinv_kernel), and
-// the chunk kernel's workgroups, 16 or 32 rows each, read S^{-1}.  Both run
-// the same arithmetic in the same order, so their results agree bit for bit.
+// the chunk kernel's workgroups, 16 or 32 rows each, read S^{-1}; the u rows
+// of each chunk are packed by column tile in the launch before the one that
+// reads them (sm_pack_kernel packs the first chunk).  Both run the same
+// arithmetic in the same order, so their results agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
