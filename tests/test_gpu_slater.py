@@ -249,6 +249,46 @@ def test_batched_equals_single_bitwise(blip):
     np.testing.assert_allclose(got_r[q, : counts[q]], want_r, rtol=1e-9)
 
 
+def test_batched_workspace_offsets_and_reuse(blip):
+    """The batched update keeps each chunk's packed u rows in its workspace:
+    a workspace that is only 16-byte aligned (a view 16 bytes into a larger
+    buffer), reused by a second call with other matrices and counts, gives
+    the same bits as a fresh 256-byte-aligned one, and a workspace view 8
+    bytes in is refused."""
+    n = 136
+    counts = [97, 40, 0, 65]
+    nmat = len(counts)
+    rng = np.random.default_rng(33)
+    invs, Us, acc = [], [], np.zeros((nmat, n), dtype=np.int32)
+    for q in range(nmat):
+        _, inv_t, _, U = case(400 + q, n, 1)
+        invs.append(inv_t)
+        Us.append(U)
+        acc[q, : counts[q]] = rng.permutation(n)[: counts[q]]
+    nbytes = blip.lib().blip_sm_batched_workspace_size(nmat, n)
+    big = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    cnt = torch.tensor(counts, dtype=torch.int32, device="cuda")
+    acc_d = torch.from_numpy(acc).cuda()
+    u_b = torch.from_numpy(np.stack(Us)).cuda()
+    say(f"batched SM workspace offsets: {nmat} matrices of order {n}, counts {counts}")
+
+    def run(ws, k=max(counts), c=cnt):
+        inv_b = torch.from_numpy(np.stack(invs)).cuda()
+        r = blip.sm_update_batched(inv_b, u_b, acc_d, c, k, workspace=ws)
+        torch.cuda.synchronize()
+        return to_np(inv_b), to_np(r)
+
+    want_inv, want_r = run(torch.empty(nbytes, dtype=torch.uint8, device="cuda"))
+    # a first call with other counts leaves other packed rows behind
+    run(big[16:16 + nbytes], k=n, c=torch.tensor([n, 3, 77, 1], dtype=torch.int32, device="cuda"))
+    got_inv, got_r = run(big[16:16 + nbytes])
+    np.testing.assert_array_equal(got_inv, want_inv)
+    for q in range(nmat):
+        np.testing.assert_array_equal(got_r[q, : counts[q]], want_r[q, : counts[q]])
+    with pytest.raises(RuntimeError, match="16-byte"):
+        run(big[8:8 + nbytes])
+
+
 @pytest.mark.parametrize("n", [200, 201])
 def test_batched_two_row_blocks_equals_single_bitwise(blip, n):
     """Enough matrices for the batched kernel to take two 16-row blocks per
