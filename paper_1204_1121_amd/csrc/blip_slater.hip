@@ -704,6 +704,14 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
     // launch (R and u both present, or only one of them), so that each
     // issues only the loads it uses, and the same loads on every path.
     auto walk = [&](auto HR, auto HU) {
+        // The ring of tile buffers lives across the column tiles of a walk: the
+        // last step of one column tile loads the first tile of the next (ring
+        // slot 0 when the column tile had an even number of steps, as every
+        // full one has), so a column tile's first wait does not expose a whole
+        // load latency.
+        static_assert(kSmAhead == 1, "the cross-column-tile prefetch assumes a ring of two");
+        TileIn buf[kSmAhead + 1];
+        bool have0 = false;   // buf[0] already holds this column tile's first tile
         for (int y = y0; y < y1; ++y) {
             const int c0 = y * a.tl;
             const int cend = min(n, c0 + a.tl);
@@ -723,17 +731,22 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
             // tile's loads outstanding.
             const int K = w < ntile ? (ntile - w + kSmWaves - 1) / kSmWaves : 0;
             auto tile_col = [&](int k) { return c0 + (w + kSmWaves * k) * kSmTile; };
-            TileIn buf[kSmAhead + 1];
+            // this wavefront's first tile of the next column tile, if any
+            const int c0n = (y + 1) * a.tl;
+            const bool nxt = y + 1 < y1 && c0n + w * kSmTile < min(n, c0n + a.tl) && K % 2 == 0;
             if (K > 0) {
+                if (!have0) {
 #pragma unroll
-                for (int j = 0; j < kSmAhead; ++j) load_tile(HR, HU, tile_col(j), j < K, buf[j]);
+                    for (int j = 0; j < kSmAhead; ++j) load_tile(HR, HU, tile_col(j), j < K, buf[j]);
+                }
                 for (int kb = 0; kb < K; kb += kSmAhead + 1) {
 #pragma unroll
                     for (int j = 0; j <= kSmAhead; ++j) {
                         const int k = kb + j;
                         if (k >= K) break;   // uniform per wavefront
-                        load_tile(HR, HU, tile_col(k + kSmAhead), k + kSmAhead < K,
-                                  buf[(j + kSmAhead) % (kSmAhead + 1)]);
+                        const bool inr = k + kSmAhead < K;
+                        load_tile(HR, HU, inr ? tile_col(k + kSmAhead) : c0n + w * kSmTile,
+                                  inr || nxt, buf[(j + kSmAhead) % (kSmAhead + 1)]);
                         const TileIn& cur = buf[j];
                         const int c = c0 + (w + kSmWaves * k) * kSmTile;
 #pragma unroll
@@ -793,6 +806,7 @@ __device__ __forceinline__ void sm_chunk_body(SmArgs a)
                     }
                 }
             }
+            have0 = K > 0 && nxt;
             if constexpr (decltype(HU)::value) {
                 // element r of vacc[rb][mb] is V[row 16 rb + 4r + g][move 16 mb + lr]
 #pragma unroll
